@@ -1,0 +1,154 @@
+"""Benchmark of the EPWI SERTA hot path on one MI355X.
+
+One step = one eph_scattering_rates call (grid tables, states, Re transform,
+fused rate kernel) + one eph_conductivity call, on the Al-like 100^3 k x
+100^3 q workload with the 100/300/500 K batch (synthetic inputs, seeded).
+
+Prints ONE JSON line:
+  value       (k,q) pairs with >= 1 kept term, per second of step time
+  ms_per_step step time = the sigma wall time (rates + conductivity)
+  roofline    the fused rate kernel against the FP64 vector peak, with the
+              flops of the algorithm it runs (from the call's own counts)
+              over its HIP-event-timed duration
+  cpu_baseline the FP64 C oracle on a seeded sample of k points (all q)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "(k,q) el-ph pair evals/s + σ wall time at ≤1e-3 rel σ error vs FP64"
+FP64_PEAK_TFLOPS = 78.6
+
+
+def rate_kernel_flops(counts, ns, N, box, C, nm, nw):
+    """FP64 flops the fused rate kernel executes (8 per complex MAC):
+    Y stage 8*ns*N*nbox*C, Z stage 8*ns*N^2*n1*n2*C, and per vertex
+    contraction 8*(n1*nm*nw + n1*nm + nm*nm).  Transcendentals (delta,
+    occupations) are not counted."""
+    n1, n2, n3 = box
+    y = 8.0 * ns * N * n1 * n2 * n3 * C
+    z = 8.0 * ns * N * N * n1 * n2 * C
+    v = 8.0 * counts["n_vertex"] * (n1 * nm * nw + n1 * nm + nm * nm)
+    return y + z + v
+
+
+def cpu_baseline(system, w, mu, lo, hi, state_k, n_pick):
+    import numpy as np
+    import oracle
+    from oracle import Oracle
+    o = Oracle(system)
+    N = w.grid
+    t0 = time.perf_counter()
+    eps, evec, vel = o.electrons(N)
+    om, u, _ = o.phonons(N)
+    t_tables = time.perf_counter() - t0
+    rng = np.random.default_rng(20240601)
+    kall = np.unique(state_k)
+    kpick = np.sort(rng.choice(kall, size=min(n_pick, kall.size), replace=False))
+    sk, sn = o.select_states(eps, w.band_lo, w.band_hi, lo, hi, k_subset=kpick)
+    t0 = time.perf_counter()
+    r = o.rates(N, eps, evec, om, u, sk, sn, mu, w.temps, w.eta)
+    t = time.perf_counter() - t0
+    return {"value": r["n_kq"] / t, "unit": "(k,q) pairs/s", "cores": int(oracle.lib().orc_num_threads()),
+            "kind": "oracle",
+            "sample": f"{kpick.size} seeded k points ({sk.size} states, {r['n_kq']} (k,q) pairs, all {N}^3 q) of "
+                      f"{w.name}; rate loop {t:.2f} s; full-grid oracle tables {t_tables:.2f} s not counted"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="al_fcc_100")
+    ap.add_argument("--grid", type=int, default=None)
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="k points of the oracle sample (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from synth import make_system, workload
+    from paper_2306_16493_amd import Context
+
+    w = workload(args.workload, args.grid)
+    s = make_system(w.system)
+    mu = s.mu_centroid
+    lo, hi = mu + w.window[0], mu + w.window[1]
+    ctx = Context(s, device=0)
+    p = ctx.params(w.grid, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision=args.precision)
+    ns = ctx.count_states(p)
+    ctx.set_profiling(True)
+    bufs = None
+    print(f"[bench] {w.name} N={w.grid} states={ns}", file=sys.stderr, flush=True)
+
+    def step():
+        nonlocal bufs
+        res, bufs = ctx.scattering_rates(p, capacity=ns, buffers=bufs)
+        sig = ctx.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, w.temps, w.grid ** 3)
+        return res, sig
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    rates_ms, xform_ms, launches = [], [], 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res, sig = step()
+        st = ctx.stage_times()
+        rates_ms.append(st["rates_ms"])
+        xform_ms.append(st["xform_ms"])
+        launches += st["rates_launches"]
+        print(f"[bench] step {i}: call {st['call_ms']:.1f} ms (tables {st['tables_ms']:.1f}, prep "
+              f"{st['prep_ms']:.1f}, xform {st['xform_ms']:.1f}, rates {st['rates_ms']:.1f})",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    counts = res.counts
+    nm, nw = 3 * s.na, s.nw
+    box = [len(np.unique(s.rp[:, a])) for a in range(3)]
+    flops = rate_kernel_flops(counts, ns, w.grid, box, nm * nw, nm, nw)
+    kern_s = np.mean(rates_ms) / 1e3
+    achieved = flops / kern_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": counts["n_kq"] / t,
+        "unit": "(k,q) pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t * 1e3,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": w.grid, "temps_K": list(w.temps), "eta_eV": w.eta,
+                   "window_eV": [lo, hi], "precision": args.precision, "n_states": ns,
+                   "n_kq": counts["n_kq"], "n_nkq": counts["n_nkq"], "n_terms": counts["n_terms"],
+                   "n_vertex": counts["n_vertex"]},
+        "sigma_wall_s": t,
+        "sigma_S_per_m_xx": [float(sig[i, 0, 0]) for i in range(sig.shape[0])],
+        "stages_ms": {"tables": st["tables_ms"], "prep": st["prep_ms"], "xform": float(np.mean(xform_ms)),
+                      "rates": float(np.mean(rates_ms)), "call": st["call_ms"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "rates_kernel<double,4,3,8>",
+                     "flops_per_step": flops, "launches_per_step": launches / args.steps},
+    }
+    if args.cpu_sample > 0:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(s, w, mu, lo, hi, res.state_k.cpu().numpy(), args.cpu_sample)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * eph.h -- C ABI of the MI355X (gfx950) electron-phonon Wannier interpolation
+ * (EPWI) SERTA transport library.
+ *
+ * The library computes, on one GPU, the quantities of arXiv 2306.16493:
+ *   - Bloch Hamiltonian H(k) = sum_R w_R e^{ik.R} H(R), its eigenpairs and
+ *     band velocities (Sec. II.B, Wannier interpolation of H; velocities are
+ *     a preprocessing quantity of Sec. III.A);
+ *   - dynamical matrix D(q) = sum_R w_R Phi(R)/sqrt(m m') e^{iq.R}, phonon
+ *     energies hbar w and displacements u_{mu nu} = (hbar/2 m_mu w)^{1/2} e
+ *     (Sec. II.B);
+ *   - the interpolated vertex g_mn^nu(k,q) (Sec. II.B), in the bracket order
+ *     of the q-batch algorithm (Sec. III.C);
+ *   - SERTA scattering rates 1/tau_nk (Sec. II.C) over energy-conserving
+ *     processes (the energy-conservation sieve of Sec. III.A);
+ *   - the conductivity tensor sigma (Sec. II.C).
+ *
+ * Conventions shared by every call
+ *   - Units: Angstrom, amu, eV, K, seconds; velocities m/s; sigma S/m.
+ *   - Complex arrays are interleaved (re, im) doubles.
+ *   - Lattice vectors are integer lattice coordinates (n1,n2,n3), R = sum n_i a_i.
+ *   - The k and q grids are the same Gamma-centred N x N x N grid; grid point
+ *     (i1,i2,i3) has reduced coordinates i/N and linear index
+ *     i1 + N*(i2 + N*i3).  k+q is the grid point (i_k + i_q) mod N.
+ *   - Eigenvectors: H V = V diag(eps), U = V^dagger, so the vertex reads
+ *     g_mn^nu(k,q) = sum conj(V_im(k+q)) V_jn(k) e^{i(k.Re+q.Rp)}
+ *                    g_ij^mu(Re,Rp) u_{mu nu}(q).
+ *   - delta_eta(x) = exp(-x^2/eta^2) / (sqrt(pi) eta); a (q, m, nu, +-)
+ *     term enters 1/tau when |eps_nk +- hbar w_qnu - eps_m,k+q| <=
+ *     sieve_width*eta and hbar w_qnu >= omega_cut.
+ *   - 1/tau carries the Brillouin-zone average 1/N^3 over q.
+ *   - Every call returns an eph_status and never throws.  On an error the
+ *     outputs are left untouched (except *counts on EPH_E_TRUNCATED) and
+ *     eph_last_error() describes it.
+ *   - A context is used by one host thread at a time.  Calls enqueue their
+ *     work on the given HIP stream (NULL = the default stream) and
+ *     synchronise that stream before they return host results.
+ */
+#ifndef EPH_H
+#define EPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eph_ctx eph_ctx;
+
+typedef enum {
+  EPH_OK = 0,
+  EPH_E_INVALID = 1,     /* bad argument, dimension or model property */
+  EPH_E_NOMEM = 2,       /* device allocation failed */
+  EPH_E_DEVICE = 3,      /* HIP runtime error (message in eph_last_error) */
+  EPH_E_STATE = 4,       /* call on a context in an unusable state */
+  EPH_E_TRUNCATED = 5,   /* output capacity too small; counts->n_states set */
+  EPH_E_UNSUPPORTED = 6  /* valid input outside the implemented shapes */
+} eph_status;
+
+typedef enum {
+  EPH_FP64 = 0,   /* every step in FP64 */
+  EPH_FP32 = 1,   /* Re and Rp transforms and rotations in FP32 (FP32 tables);
+                     eigensolves, energies, the sieve and the 1/tau and sigma
+                     accumulations in FP64 */
+  EPH_BF16X3 = 2  /* as EPH_FP32, but the Re transform on bf16 MFMA with the
+                     split x = hi + lo and three products hi*hi + hi*lo +
+                     lo*hi accumulated in FP32 */
+} eph_precision;
+
+/* Limits of this implementation (EPH_E_UNSUPPORTED beyond them). */
+#define EPH_MAX_WANN 8   /* Wannier orbitals: 1, 2, 4 or 8 */
+#define EPH_MAX_MODES 6  /* phonon modes 3*n_atoms: 3 or 6 */
+#define EPH_MAX_TEMPS 4  /* temperatures per rates call */
+#define EPH_MAX_GRID 512 /* N of the N x N x N grid */
+
+/* The Wannier-basis model.  All pointers are HOST pointers; the data is
+ * copied to the device by eph_load_wannier and the caller keeps ownership.
+ *   lattice   rows a1, a2, a3 (Angstrom)
+ *   mass_amu  [n_atoms]
+ *   rh, rh_w  [n_rh][3] lattice coordinates and weights of H(R); the set
+ *             must be closed under R -> -R with w(-R) = w(R)
+ *   ham       [n_rh][n_wann][n_wann] complex, eV; H(-R) = H(R)^dagger
+ *   rd, rd_w  [n_rd][3], weights; same closure rule
+ *   ifc       [n_rd][3 n_atoms][3 n_atoms] real, eV/A^2, index 3*atom+axis;
+ *             Phi(-R) = Phi(R)^T
+ *   re        [n_re][3] electron lattice vectors of g (any set)
+ *   rp        [n_rp][3] phonon lattice vectors of g; must form a full box
+ *             {lo_i .. lo_i + n_i - 1} per coordinate (n_i <= 16), any order
+ *   gw        [n_re][n_rp][3 n_atoms][n_wann(i)][n_wann(j)] complex, eV/A
+ *             (g_ij^mu(Re, Rp)); i pairs with k+q, j with k.            */
+typedef struct {
+  double lattice[9];
+  int32_t n_atoms;
+  const double *mass_amu;
+  int32_t n_wann;
+  int32_t n_rh;
+  const int32_t *rh;
+  const double *rh_w;
+  const double *ham;
+  int32_t n_rd;
+  const int32_t *rd;
+  const double *rd_w;
+  const double *ifc;
+  int32_t n_re;
+  const int32_t *re;
+  int32_t n_rp;
+  const int32_t *rp;
+  const double *gw;
+} eph_model;
+
+/* Validate the model (Hermiticity of H(R) and Phi(R) pairs to 1e-12 of the
+ * largest element, closure of the R sets, positive weights and masses,
+ * dimensions), select HIP device `device`, copy the model to it and return
+ * a new context in *out.  Errors: EPH_E_INVALID, EPH_E_UNSUPPORTED,
+ * EPH_E_NOMEM, EPH_E_DEVICE; *out is set to NULL on error.  The paper's
+ * input stage (Sec. III.A) reads these Wannier-basis quantities from EPW. */
+int32_t eph_load_wannier(const eph_model *model, int32_t device, eph_ctx **out);
+
+/* Release a context and all its device memory.  NULL is accepted. */
+void eph_free(eph_ctx *ctx);
+
+/* Message of the last failed call on ctx (or of the last failed
+ * eph_load_wannier in this thread when ctx is NULL).  Valid until the next
+ * call on the same context. */
+const char *eph_last_error(const eph_ctx *ctx);
+
+typedef struct {
+  int32_t grid[3];          /* N, N, N (all three equal, 1..EPH_MAX_GRID) */
+  double mu_eV;             /* chemical potential */
+  int32_t n_temps;          /* 1..EPH_MAX_TEMPS */
+  const double *temps_K;    /* host [n_temps], each > 0 */
+  double eta_eV;            /* Gaussian smearing, > 0 */
+  double sieve_width;       /* keep |x| <= sieve_width*eta; > 0 (6 is usual) */
+  double win_lo_eV;         /* state window on eps_nk (inclusive) */
+  double win_hi_eV;
+  int32_t band_lo;          /* initial-state bands band_lo..band_hi */
+  int32_t band_hi;          /* < 0 means the last band */
+  double omega_cut_eV;      /* phonon modes below are dropped (>= 0) */
+  int32_t precision;        /* eph_precision */
+  const int64_t *k_subset;  /* optional host list of k indices whose window
+                               states are computed (duplicates ignored);
+                               NULL = every k of the grid */
+  int64_t n_k_subset;
+  void *stream;             /* hipStream_t, NULL = default stream */
+} eph_rates_params;
+
+typedef struct {
+  int64_t n_states;          /* initial states (n,k) selected */
+  int64_t n_kq;              /* (k,q) pairs with >= 1 kept term for a state at k */
+  int64_t n_nkq;             /* (n,k,q) with >= 1 kept term */
+  int64_t n_terms;           /* kept (n,k,q,m,nu,+-) terms */
+  int64_t n_zero_rate;       /* states whose 1/tau is 0 at the first temperature */
+  int64_t n_excluded_modes;  /* (q,nu) with hbar w < omega_cut on the grid */
+  int64_t n_vertex;          /* (n,k,q,m) vertex contractions evaluated: final
+                                bands m with >= 1 kept (nu, +-) term */
+} eph_counts;
+
+/* SERTA scattering rates (Sec. II.C) of every selected state.
+ * States are the (n,k) with band_lo <= n <= band_hi and
+ * win_lo_eV <= eps_nk <= win_hi_eV (k restricted to k_subset if given),
+ * ordered by k index, then n.
+ * Outputs are caller-owned DEVICE buffers on the context's device:
+ *   state_k [capacity] int32, state_n [capacity] int32,
+ *   energy_eV [capacity], vel_ms [capacity][3],
+ *   inv_tau_s [n_temps][n_states] (packed with stride n_states), 1/s.
+ * counts is a host pointer (may be NULL).
+ * If capacity < n_states nothing is written except *counts (n_states set,
+ * the other counts 0) and EPH_E_TRUNCATED is returned; calling with
+ * capacity 0 is the way to size the outputs.
+ * Every grid quantity (eigenpairs, velocities, phonons) is recomputed from
+ * the Wannier model by each call. */
+int32_t eph_scattering_rates(eph_ctx *ctx, const eph_rates_params *params, int64_t capacity,
+                             int32_t *state_k, int32_t *state_n, double *energy_eV,
+                             double *vel_ms, double *inv_tau_s, eph_counts *counts);
+
+/* Conductivity tensor (Sec. II.C) from per-state data, in S/m:
+ *   sigma_ab(T) = 2 e^2/(n_kpoints V) sum_s v_a v_b tau_s f(1-f)/(k_B T),
+ * tau_s = 1/inv_tau_s(T); states with inv_tau = 0 are skipped.  V is the
+ * cell volume of the loaded lattice.
+ * energy_eV [n_states], vel_ms [n_states][3], inv_tau_s [n_temps][n_states]
+ * are DEVICE pointers (e.g. the outputs of eph_scattering_rates, a
+ * surrogate's rates, or a constant-tau test); temps_K and sigma_S_per_m
+ * ([n_temps][3][3]) are HOST pointers.  The reduction is FP64 in a fixed
+ * order, so repeated calls give bit-identical results. */
+int32_t eph_conductivity(eph_ctx *ctx, int64_t n_states, const double *energy_eV,
+                         const double *vel_ms, const double *inv_tau_s, double mu_eV,
+                         int32_t n_temps, const double *temps_K, int64_t n_kpoints,
+                         void *stream, double *sigma_S_per_m);
+
+/* Stage timing.  With profiling on, eph_scattering_rates records HIP events
+ * on its stream around its stages; eph_stage_times then returns their GPU
+ * durations in milliseconds for the last call:
+ *   ms[0] grid tables (Bloch sums, eigensolves, velocities, phonons)
+ *   ms[1] state selection, grouping, energy-sorted lines
+ *   ms[2] Re transform (all launches)
+ *   ms[3] rate kernel (all launches)
+ *   ms[4] whole call (first to last event)
+ * and in launches[0] / launches[1] the number of Re-transform and
+ * rate-kernel launches.  ms needs 5 doubles, launches 2 int64 (host).
+ * Profiling is off by default; it adds event records but no
+ * synchronisation beyond the one each call already does. */
+int32_t eph_set_profiling(eph_ctx *ctx, int32_t on);
+int32_t eph_stage_times(const eph_ctx *ctx, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPH_H */

@@ -468,3 +468,15 @@ void orc_carrier_density(int64_t nk, int nw, const double *eps, int band_lo, int
     nc[t] = 2.0 * acc / ((double)nk * volume_a3 * 1e-30);
   }
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* threads an OpenMP region of the oracle uses */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

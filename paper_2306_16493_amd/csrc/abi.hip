@@ -1,0 +1,534 @@
+// C ABI of the gfx950 EPWI transport library: model validation and upload,
+// orchestration of the kernels of one scattering-rates call, conductivity.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "internal.h"
+
+namespace eph {
+
+Units units() {
+  Units u;
+  const double hbar = kPlanck / (2.0 * kPi);
+  u.hbar_evs = hbar / kCharge;
+  u.kb_evk = kBoltz / kCharge;
+  u.cph_ev = hbar * hbar / (kAmu * 1e-20) / kCharge;
+  u.vel_unit = kCharge * 1e-10 / hbar;
+  u.rate_pref = 2.0 * kPi / u.hbar_evs;
+  return u;
+}
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+
+hipError_t DevBuf::ensure(size_t n) {
+  if (n <= bytes && p) return hipSuccess;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+  if (n == 0) n = 8;
+  hipError_t e = hipMalloc(&p, n);
+  if (e == hipSuccess) bytes = n;
+  else p = nullptr;
+  return e;
+}
+
+}  // namespace eph
+
+using namespace eph;
+
+namespace {
+
+thread_local std::string g_load_error;
+
+int fail(eph_ctx *c, int code, const std::string &msg) {
+  c->err = msg;
+  return code;
+}
+
+int hip_fail(eph_ctx *c, hipError_t e, const char *what) {
+  (void)hipGetLastError();
+  return fail(c, e == hipErrorOutOfMemory ? EPH_E_NOMEM : EPH_E_DEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define EPH_HIP(ctx, expr)                                 \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+  } while (0)
+
+using Vec3 = std::tuple<int, int, int>;
+
+// Event recorder for stage timing; a no-op unless profiling is on.
+struct Timer {
+  eph_ctx *c;
+  hipStream_t st;
+  int used = 0;
+  hipError_t mark(int *slot) {
+    *slot = -1;
+    if (!c->profiling) return hipSuccess;
+    if ((int)c->ev.size() <= used) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      c->ev.push_back(e);
+    }
+    *slot = used;
+    return hipEventRecord(c->ev[used++], st);
+  }
+  float ms(int a, int b) const {
+    float t = 0.f;
+    if (a >= 0 && b >= 0) (void)hipEventElapsedTime(&t, c->ev[a], c->ev[b]);
+    return t;
+  }
+};
+
+template <class T>
+hipError_t upload(DevBuf &b, const T *host, size_t n) {
+  hipError_t e = b.ensure(sizeof(T) * n);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(b.p, host, sizeof(T) * n, hipMemcpyHostToDevice);
+}
+
+// Checks that the R set is closed under negation with equal weights and
+// that M(-R) = M(R)^dagger (herm=true, complex) or M(R)^T (real).
+std::string check_pairs(int nr, const int32_t *R, const double *w, const double *M, int n, bool cplx) {
+  std::map<Vec3, int> idx;
+  for (int r = 0; r < nr; r++) {
+    Vec3 v{R[3 * r], R[3 * r + 1], R[3 * r + 2]};
+    if (idx.count(v)) return "duplicate lattice vector";
+    idx[v] = r;
+    if (!(w[r] > 0.0) || !std::isfinite(w[r])) return "weights must be positive";
+  }
+  const int es = cplx ? 2 : 1;
+  double mx = 0.0;
+  for (size_t e = 0; e < (size_t)nr * n * n * es; e++) {
+    if (!std::isfinite(M[e])) return "non-finite matrix element";
+    mx = std::max(mx, std::fabs(M[e]));
+  }
+  for (int r = 0; r < nr; r++) {
+    Vec3 neg{-R[3 * r], -R[3 * r + 1], -R[3 * r + 2]};
+    auto it = idx.find(neg);
+    if (it == idx.end()) return "lattice-vector set not closed under R -> -R";
+    int q = it->second;
+    if (w[q] != w[r]) return "weights differ between R and -R";
+    for (int i = 0; i < n; i++)
+      for (int j = 0; j < n; j++) {
+        // M(-R)_ij == conj(M(R)_ji)
+        double ar = M[((size_t)q * n * n + i * n + j) * es];
+        double br = M[((size_t)r * n * n + j * n + i) * es];
+        double d = std::fabs(ar - br);
+        if (cplx) {
+          double ai = M[((size_t)q * n * n + i * n + j) * es + 1];
+          double bi = M[((size_t)r * n * n + j * n + i) * es + 1];
+          d = std::max(d, std::fabs(ai + bi));
+        }
+        if (d > 1e-12 * mx) return cplx ? "H(-R) != H(R)^dagger" : "Phi(-R) != Phi(R)^T";
+      }
+  }
+  return "";
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *eph_last_error(const eph_ctx *ctx) { return ctx ? ctx->err.c_str() : g_load_error.c_str(); }
+
+void eph_free(eph_ctx *ctx) {
+  if (!ctx) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+  (void)hipSetDevice(cur);
+}
+
+int32_t eph_load_wannier(const eph_model *m, int32_t device, eph_ctx **out) {
+  if (!out) {
+    g_load_error = "out is NULL";
+    return EPH_E_INVALID;
+  }
+  *out = nullptr;
+  eph_ctx *c = new eph_ctx();
+  auto bad = [&](int code, const std::string &msg) {
+    g_load_error = msg;
+    delete c;
+    return code;
+  };
+  if (!m) return bad(EPH_E_INVALID, "model is NULL");
+  if (m->n_wann < 1 || m->n_atoms < 1 || m->n_rh < 1 || m->n_rd < 1 || m->n_re < 1 || m->n_rp < 1)
+    return bad(EPH_E_INVALID, "dimensions must be positive");
+  if (!m->mass_amu || !m->rh || !m->rh_w || !m->ham || !m->rd || !m->rd_w || !m->ifc || !m->re || !m->rp || !m->gw)
+    return bad(EPH_E_INVALID, "NULL model array");
+  if (m->n_wann > EPH_MAX_WANN) return bad(EPH_E_UNSUPPORTED, "n_wann above EPH_MAX_WANN");
+  if (3 * m->n_atoms > EPH_MAX_MODES) return bad(EPH_E_UNSUPPORTED, "3*n_atoms above EPH_MAX_MODES");
+  const int nw = m->n_wann, na = m->n_atoms, nm = 3 * na;
+  if (!(nw == 1 || nw == 2 || nw == 4 || nw == 8)) return bad(EPH_E_UNSUPPORTED, "n_wann must be 1, 2, 4 or 8");
+  for (int a = 0; a < na; a++)
+    if (!(m->mass_amu[a] > 0.0) || !std::isfinite(m->mass_amu[a])) return bad(EPH_E_INVALID, "masses must be positive");
+  double vol = m->lattice[0] * (m->lattice[4] * m->lattice[8] - m->lattice[5] * m->lattice[7]) -
+               m->lattice[1] * (m->lattice[3] * m->lattice[8] - m->lattice[5] * m->lattice[6]) +
+               m->lattice[2] * (m->lattice[3] * m->lattice[7] - m->lattice[4] * m->lattice[6]);
+  if (!(std::fabs(vol) > 0.0) || !std::isfinite(vol)) return bad(EPH_E_INVALID, "degenerate lattice");
+  std::string why = check_pairs(m->n_rh, m->rh, m->rh_w, m->ham, nw, true);
+  if (!why.empty()) return bad(EPH_E_INVALID, "H: " + why);
+  why = check_pairs(m->n_rd, m->rd, m->rd_w, m->ifc, nm, false);
+  if (!why.empty()) return bad(EPH_E_INVALID, "Phi: " + why);
+  // Rp must be a full box
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; a++) lo[a] = hi[a] = m->rp[a];
+  for (int r = 0; r < m->n_rp; r++)
+    for (int a = 0; a < 3; a++) {
+      lo[a] = std::min(lo[a], m->rp[3 * r + a]);
+      hi[a] = std::max(hi[a], m->rp[3 * r + a]);
+    }
+  RpBox box;
+  for (int a = 0; a < 3; a++) {
+    box.lo[a] = lo[a];
+    box.n[a] = hi[a] - lo[a] + 1;
+    if (box.n[a] > 16) return bad(EPH_E_UNSUPPORTED, "Rp box edge above 16");
+  }
+  if ((int64_t)box.count() != m->n_rp) return bad(EPH_E_UNSUPPORTED, "Rp vectors must form a full box");
+  std::vector<int> rp_pos(m->n_rp);
+  {
+    std::vector<char> seen(box.count(), 0);
+    for (int r = 0; r < m->n_rp; r++) {
+      int p = ((m->rp[3 * r] - lo[0]) * box.n[1] + (m->rp[3 * r + 1] - lo[1])) * box.n[2] + (m->rp[3 * r + 2] - lo[2]);
+      if (seen[p]) return bad(EPH_E_INVALID, "duplicate Rp vector");
+      seen[p] = 1;
+      rp_pos[r] = p;
+    }
+  }
+  for (size_t e = 0; e < (size_t)m->n_re * m->n_rp * nm * nw * nw * 2; e++)
+    if (!std::isfinite(m->gw[e])) return bad(EPH_E_INVALID, "non-finite g");
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return bad(EPH_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return bad(EPH_E_INVALID, "device index out of range");
+  if (hipSetDevice(device) != hipSuccess) return bad(EPH_E_DEVICE, "hipSetDevice failed");
+
+  c->device = device;
+  c->nw = nw;
+  c->na = na;
+  c->nm = nm;
+  std::memcpy(c->lattice, m->lattice, sizeof(c->lattice));
+  c->volume = std::fabs(vol);
+  c->nrh = m->n_rh;
+  c->nrd = m->n_rd;
+  c->nre = m->n_re;
+  c->nrp = m->n_rp;
+  c->box = box;
+  c->mode_mass.resize(nm);
+  for (int mu = 0; mu < nm; mu++) c->mode_mass[mu] = m->mass_amu[mu / 3];
+
+  // H: vectors, weights, Cartesian vectors, matrices
+  std::vector<double> cart(3 * (size_t)m->n_rh);
+  for (int r = 0; r < m->n_rh; r++)
+    for (int a = 0; a < 3; a++)
+      cart[3 * r + a] = m->rh[3 * r] * m->lattice[a] + m->rh[3 * r + 1] * m->lattice[3 + a] +
+                        m->rh[3 * r + 2] * m->lattice[6 + a];
+  // Phi / sqrt(M M') as complex
+  std::vector<double> dyn(2 * (size_t)m->n_rd * nm * nm, 0.0);
+  for (int r = 0; r < m->n_rd; r++)
+    for (int a = 0; a < nm; a++)
+      for (int b = 0; b < nm; b++)
+        dyn[2 * (((size_t)r * nm + a) * nm + b)] =
+            m->ifc[((size_t)r * nm + a) * nm + b] / std::sqrt(c->mode_mass[a] * c->mode_mass[b]);
+  // g: Wt[(re, j)][(rp_box, mu, i)]
+  const size_t ncol = (size_t)box.count() * nm * nw, K = (size_t)m->n_re * nw;
+  std::vector<double> wt(2 * K * ncol);
+  for (int r = 0; r < m->n_re; r++)
+    for (int p = 0; p < m->n_rp; p++)
+      for (int mu = 0; mu < nm; mu++)
+        for (int i = 0; i < nw; i++)
+          for (int j = 0; j < nw; j++) {
+            size_t src = ((((size_t)r * m->n_rp + p) * nm + mu) * nw + i) * nw + j;
+            size_t dst = ((size_t)r * nw + j) * ncol + ((size_t)rp_pos[p] * nm + mu) * nw + i;
+            wt[2 * dst] = m->gw[2 * src];
+            wt[2 * dst + 1] = m->gw[2 * src + 1];
+          }
+  hipError_t e;
+  if ((e = upload(c->rh, m->rh, 3 * (size_t)m->n_rh)) != hipSuccess ||
+      (e = upload(c->rh_w, m->rh_w, (size_t)m->n_rh)) != hipSuccess ||
+      (e = upload(c->rh_cart, cart.data(), cart.size())) != hipSuccess ||
+      (e = upload(c->ham, m->ham, 2 * (size_t)m->n_rh * nw * nw)) != hipSuccess ||
+      (e = upload(c->rd, m->rd, 3 * (size_t)m->n_rd)) != hipSuccess ||
+      (e = upload(c->rd_w, m->rd_w, (size_t)m->n_rd)) != hipSuccess ||
+      (e = upload(c->dyn, dyn.data(), dyn.size())) != hipSuccess ||
+      (e = upload(c->re, m->re, 3 * (size_t)m->n_re)) != hipSuccess ||
+      (e = upload(c->wt64, wt.data(), wt.size())) != hipSuccess ||
+      (e = upload(c->mode_mass_d, c->mode_mass.data(), c->mode_mass.size())) != hipSuccess) {
+    (void)hipGetLastError();
+    return bad(e == hipErrorOutOfMemory ? EPH_E_NOMEM : EPH_E_DEVICE,
+               std::string("upload: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return EPH_OK;
+}
+
+int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
+                             int32_t *state_n, double *energy_eV, double *vel_ms, double *inv_tau_s,
+                             eph_counts *counts) {
+  if (!c) return EPH_E_INVALID;
+  c->err.clear();
+  if (!p) return fail(c, EPH_E_INVALID, "params is NULL");
+  const int N = p->grid[0];
+  if (N < 1 || p->grid[1] != N || p->grid[2] != N) return fail(c, EPH_E_INVALID, "grid must be N x N x N, N >= 1");
+  if (N > EPH_MAX_GRID) return fail(c, EPH_E_UNSUPPORTED, "grid above EPH_MAX_GRID");
+  if (p->n_temps < 1 || p->n_temps > EPH_MAX_TEMPS || !p->temps_K)
+    return fail(c, EPH_E_INVALID, "n_temps must be 1..EPH_MAX_TEMPS with temps_K given");
+  for (int t = 0; t < p->n_temps; t++)
+    if (!(p->temps_K[t] > 0.0) || !std::isfinite(p->temps_K[t])) return fail(c, EPH_E_INVALID, "temperatures must be > 0");
+  if (!(p->eta_eV > 0.0) || !std::isfinite(p->eta_eV)) return fail(c, EPH_E_INVALID, "eta must be > 0");
+  if (!(p->sieve_width > 0.0) || !std::isfinite(p->sieve_width)) return fail(c, EPH_E_INVALID, "sieve_width must be > 0");
+  if (!(p->omega_cut_eV >= 0.0) || !std::isfinite(p->omega_cut_eV)) return fail(c, EPH_E_INVALID, "omega_cut must be >= 0");
+  if (!std::isfinite(p->mu_eV) || std::isnan(p->win_lo_eV) || std::isnan(p->win_hi_eV))
+    return fail(c, EPH_E_INVALID, "mu / window must be numbers");
+  if (p->precision != EPH_FP64 && p->precision != EPH_FP32 && p->precision != EPH_BF16X3)
+    return fail(c, EPH_E_INVALID, "unknown precision");
+  if (p->precision != EPH_FP64) return fail(c, EPH_E_UNSUPPORTED, "reduced-precision forms not built");
+  const int blo = p->band_lo, bhi = p->band_hi < 0 ? c->nw - 1 : p->band_hi;
+  if (blo < 0 || blo > bhi || bhi >= c->nw) return fail(c, EPH_E_INVALID, "band range outside 0..n_wann-1");
+  if (capacity < 0) return fail(c, EPH_E_INVALID, "capacity < 0");
+  if (capacity > 0 && (!state_k || !state_n || !energy_eV || !vel_ms || !inv_tau_s))
+    return fail(c, EPH_E_INVALID, "NULL output buffer");
+  const int64_t NQ = (int64_t)N * N * N;
+  std::vector<int64_t> klist;
+  if (p->k_subset) {
+    if (p->n_k_subset < 0) return fail(c, EPH_E_INVALID, "n_k_subset < 0");
+    klist.assign(p->k_subset, p->k_subset + p->n_k_subset);
+    for (int64_t k : klist)
+      if (k < 0 || k >= NQ) return fail(c, EPH_E_INVALID, "k_subset index outside the grid");
+    std::sort(klist.begin(), klist.end());
+    klist.erase(std::unique(klist.begin(), klist.end()), klist.end());
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(p->stream);
+  const Units U = units();
+  const int nw = c->nw, nm = c->nm;
+  Timer tm{c, st};
+  int e_start, e_tables = -1, e_prep = -1, e_end;
+  std::vector<int> e_batch;  // per batch: before transform, after transform, after rates
+  for (auto &x : c->stage_ms) x = 0.0;
+  c->launches[0] = c->launches[1] = 0;
+  EPH_HIP(c, tm.mark(&e_start));
+
+  // ---- grid tables: electrons and phonons on the full grid ----
+  EPH_HIP(c, c->tab.ensure(sizeof(double2) * N));
+  EPH_HIP(c, c->eps.ensure(sizeof(double) * NQ * nw));
+  EPH_HIP(c, c->evec.ensure(sizeof(double2) * NQ * nw * nw));
+  EPH_HIP(c, c->vel.ensure(sizeof(double) * NQ * nw * 3));
+  EPH_HIP(c, c->om.ensure(sizeof(double) * NQ * nm));
+  EPH_HIP(c, c->uu.ensure(sizeof(double2) * NQ * nm * nm));
+  EPH_HIP(c, c->counters.ensure(sizeof(unsigned long long) * 8));
+  unsigned long long *ctr = c->counters.as<unsigned long long>();
+  // ctr: 0 n_excluded, 1 max omega bits, 2 n_kq, 3 sum n_q_valid, 4 sum n_terms, 5 n_zero,
+  //      6 vertex contractions
+  EPH_HIP(c, launch_zero(ctr, sizeof(unsigned long long) * 8, st));
+  EPH_HIP(c, launch_phase_table(N, c->tab.as<double2>(), st));
+  EPH_HIP(c, launch_bloch_eig(0, nw, N, 0, NQ, c->nrh, c->rh.as<int>(), c->rh_w.as<double>(), c->rh_cart.as<double>(),
+                              c->ham.as<double2>(), c->tab.as<double2>(), nullptr, U.cph_ev, 0.0, U.vel_unit,
+                              c->eps.as<double>(), c->evec.as<double2>(), c->vel.as<double>(), nullptr, st));
+  EPH_HIP(c, launch_bloch_eig(1, nm, N, 0, NQ, c->nrd, c->rd.as<int>(), c->rd_w.as<double>(), nullptr,
+                              c->dyn.as<double2>(), c->tab.as<double2>(), c->mode_mass_d.as<double>(), U.cph_ev,
+                              p->omega_cut_eV, U.vel_unit, c->om.as<double>(), c->uu.as<double2>(), nullptr, ctr + 0,
+                              st));
+  EPH_HIP(c, tm.mark(&e_tables));
+
+  // ---- states in the window ----
+  const int64_t nkl = p->k_subset ? (int64_t)klist.size() : NQ;
+  const int64_t *d_klist = nullptr;
+  if (p->k_subset) {
+    EPH_HIP(c, c->subset.ensure(sizeof(int64_t) * std::max<int64_t>(1, nkl)));
+    if (nkl > 0) EPH_HIP(c, hipMemcpyAsync(c->subset.p, klist.data(), sizeof(int64_t) * nkl, hipMemcpyHostToDevice, st));
+    d_klist = c->subset.as<int64_t>();
+  }
+  EPH_HIP(c, c->cnt.ensure(sizeof(int64_t) * (nkl + 1)));
+  EPH_HIP(c, c->offs.ensure(sizeof(int64_t) * (nkl + 1)));
+  EPH_HIP(c, c->scan_tmp.ensure(sizeof(int64_t) * scan_tmp_elems(nkl + 1)));
+  EPH_HIP(c, launch_zero(c->cnt.as<int64_t>() + nkl, sizeof(int64_t), st));
+  EPH_HIP(c, launch_count_states(nkl, d_klist, nw, c->eps.as<double>(), blo, bhi, p->win_lo_eV, p->win_hi_eV,
+                                 c->cnt.as<int64_t>(), st));
+  EPH_HIP(c, launch_scan(nkl + 1, c->cnt.as<int64_t>(), c->offs.as<int64_t>(), c->scan_tmp.as<int64_t>(), st));
+  int64_t ns = 0;
+  EPH_HIP(c, hipMemcpyAsync(&ns, c->offs.as<int64_t>() + nkl, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  EPH_HIP(c, hipStreamSynchronize(st));
+  eph_counts cn;
+  std::memset(&cn, 0, sizeof(cn));
+  cn.n_states = ns;
+  if (capacity < ns) {
+    if (counts) *counts = cn;
+    return fail(c, EPH_E_TRUNCATED, "capacity below the number of states");
+  }
+  EPH_HIP(c, launch_write_states(nkl, d_klist, nw, c->eps.as<double>(), c->vel.as<double>(), blo, bhi, p->win_lo_eV,
+                                 p->win_hi_eV, c->offs.as<int64_t>(), state_k, state_n, energy_eV, vel_ms, st));
+
+  if (ns > 0) {
+    // ---- groups of states sharing a k-line ----
+    const int gmax = rates_group_max(nw, nm);
+    EPH_HIP(c, c->grp_tmp.ensure(sizeof(int64_t) * 2 * (ns + 1)));
+    int64_t *flag = c->grp_tmp.as<int64_t>(), *pos = flag + ns + 1;
+    EPH_HIP(c, c->scan_tmp.ensure(sizeof(int64_t) * std::max(scan_tmp_elems(nkl + 1), scan_tmp_elems(ns))));
+    EPH_HIP(c, launch_group_heads(ns, state_k, N, gmax, flag, st));
+    EPH_HIP(c, launch_scan(ns, flag, pos, c->scan_tmp.as<int64_t>(), st));
+    int64_t lastpf[2];
+    EPH_HIP(c, hipMemcpyAsync(&lastpf[0], pos + ns - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    EPH_HIP(c, hipMemcpyAsync(&lastpf[1], flag + ns - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    EPH_HIP(c, hipStreamSynchronize(st));
+    const int64_t ng = lastpf[0] + lastpf[1];
+    EPH_HIP(c, c->grp_start.ensure(sizeof(int64_t) * (ng + 1)));
+    int64_t *gstart = c->grp_start.as<int64_t>();
+    EPH_HIP(c, launch_group_starts(ns, flag, pos, gstart, st));
+    std::vector<int64_t> hg(ng + 1);
+    EPH_HIP(c, hipMemcpyAsync(hg.data(), gstart, sizeof(int64_t) * (ng + 1), hipMemcpyDeviceToHost, st));
+
+    // ---- energy-sorted final-state lines; largest phonon energy ----
+    EPH_HIP(c, c->line_e.ensure(sizeof(double) * NQ * nw));
+    EPH_HIP(c, c->line_key.ensure(sizeof(uint16_t) * NQ * nw));
+    EPH_HIP(c, launch_line_sort(N, nw, c->eps.as<double>(), c->line_e.as<double>(), c->line_key.as<uint16_t>(), st));
+    EPH_HIP(c, launch_max_nonneg(NQ * nm, c->om.as<double>(), ctr + 1, st));
+    EPH_HIP(c, tm.mark(&e_prep));
+    unsigned long long wbits = 0;
+    EPH_HIP(c, hipMemcpyAsync(&wbits, ctr + 1, sizeof(wbits), hipMemcpyDeviceToHost, st));
+    EPH_HIP(c, hipStreamSynchronize(st));
+    double wmax;
+    std::memcpy(&wmax, &wbits, sizeof(wmax));
+
+    // ---- per batch of groups: Re transform, then the fused rate kernel ----
+    const size_t xrow = (size_t)c->box.count() * nm * nw * sizeof(double2);
+    const size_t budget = (size_t)8 << 30;
+    int64_t max_states = std::max<int64_t>(gmax, (int64_t)(budget / xrow));
+    EPH_HIP(c, c->state_cnt.ensure(sizeof(int64_t) * 2 * ns));
+    RatesArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.N = N;
+    a.nw = nw;
+    a.nm = nm;
+    a.nt = p->n_temps;
+    a.box = c->box;
+    a.mu = p->mu_eV;
+    a.eta = p->eta_eV;
+    a.sw = p->sieve_width;
+    a.wcut = p->omega_cut_eV;
+    a.wmax = wmax;
+    for (int t = 0; t < p->n_temps; t++) a.temps_kt[t] = U.kb_evk * p->temps_K[t];
+    a.pref = U.rate_pref / (double)NQ;
+    a.sk = state_k;
+    a.sn = state_n;
+    a.eps = c->eps.as<double>();
+    a.om = c->om.as<double>();
+    a.evec = c->evec.as<double2>();
+    a.uu = c->uu.as<double2>();
+    a.line_e = c->line_e.as<double>();
+    a.line_key = c->line_key.as<uint16_t>();
+    a.tab = c->tab.as<double2>();
+    a.inv_tau = inv_tau_s;
+    a.ns_total = ns;
+    a.st_counts = c->state_cnt.as<int64_t>();
+    a.n_kq = ctr + 2;
+    a.n_vertex = ctr + 6;
+    const int ncol = c->box.count() * nm * nw;
+    int64_t g0 = 0;
+    while (g0 < ng) {
+      int64_t g1 = g0 + 1;
+      while (g1 < ng && hg[g1 + 1] - hg[g0] <= max_states) g1++;
+      const int64_t sa = hg[g0], sb = hg[g1];
+      EPH_HIP(c, c->xbuf.ensure(xrow * (size_t)(sb - sa)));
+      int eb0, eb1, eb2;
+      EPH_HIP(c, tm.mark(&eb0));
+      EPH_HIP(c, launch_xform64(sb - sa, state_k + sa, state_n + sa, N, nw, c->nre, c->re.as<int>(), ncol,
+                                c->wt64.as<double2>(), c->evec.as<double2>(), c->tab.as<double2>(),
+                                c->xbuf.as<double2>(), st));
+      a.ng = g1 - g0;
+      a.gstart = gstart + g0;
+      a.s_base = sa;
+      a.X = c->xbuf.p;
+      EPH_HIP(c, tm.mark(&eb1));
+      EPH_HIP(c, launch_rates(EPH_FP64, a, st));
+      EPH_HIP(c, tm.mark(&eb2));
+      e_batch.insert(e_batch.end(), {eb0, eb1, eb2});
+      c->launches[0]++;
+      c->launches[1]++;
+      g0 = g1;
+    }
+    EPH_HIP(c, launch_summarize(ns, c->state_cnt.as<int64_t>(), inv_tau_s, ctr + 3, st));
+  }
+  unsigned long long hc[8];
+  EPH_HIP(c, tm.mark(&e_end));
+  EPH_HIP(c, hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+  EPH_HIP(c, hipStreamSynchronize(st));
+  if (c->profiling) {
+    c->stage_ms[0] = tm.ms(e_start, e_tables);
+    c->stage_ms[1] = tm.ms(e_tables, e_prep);
+    for (size_t b = 0; b + 2 < e_batch.size(); b += 3) {
+      c->stage_ms[2] += tm.ms(e_batch[b], e_batch[b + 1]);
+      c->stage_ms[3] += tm.ms(e_batch[b + 1], e_batch[b + 2]);
+    }
+    c->stage_ms[4] = tm.ms(e_start, e_end);
+  }
+  cn.n_excluded_modes = (int64_t)hc[0];
+  cn.n_kq = (int64_t)hc[2];
+  cn.n_nkq = (int64_t)hc[3];
+  cn.n_terms = (int64_t)hc[4];
+  cn.n_zero_rate = (int64_t)hc[5];
+  cn.n_vertex = (int64_t)hc[6];
+  if (counts) *counts = cn;
+  return EPH_OK;
+}
+
+int32_t eph_set_profiling(eph_ctx *c, int32_t on) {
+  if (!c) return EPH_E_INVALID;
+  c->profiling = on != 0;
+  return EPH_OK;
+}
+
+int32_t eph_stage_times(const eph_ctx *c, double *ms, int64_t *launches) {
+  if (!c || !ms || !launches) return EPH_E_INVALID;
+  for (int i = 0; i < 5; i++) ms[i] = c->stage_ms[i];
+  launches[0] = c->launches[0];
+  launches[1] = c->launches[1];
+  return EPH_OK;
+}
+
+int32_t eph_conductivity(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
+                         const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K,
+                         int64_t n_kpoints, void *stream, double *sigma_S_per_m) {
+  if (!c) return EPH_E_INVALID;
+  c->err.clear();
+  if (n_states < 0) return fail(c, EPH_E_INVALID, "n_states < 0");
+  if (n_temps < 1 || n_temps > EPH_MAX_TEMPS || !temps_K) return fail(c, EPH_E_INVALID, "bad temperatures");
+  for (int t = 0; t < n_temps; t++)
+    if (!(temps_K[t] > 0.0) || !std::isfinite(temps_K[t])) return fail(c, EPH_E_INVALID, "temperatures must be > 0");
+  if (n_kpoints < 1) return fail(c, EPH_E_INVALID, "n_kpoints must be >= 1");
+  if (!sigma_S_per_m) return fail(c, EPH_E_INVALID, "sigma output is NULL");
+  if (n_states > 0 && (!energy_eV || !vel_ms || !inv_tau_s)) return fail(c, EPH_E_INVALID, "NULL input buffer");
+  if (!std::isfinite(mu_eV)) return fail(c, EPH_E_INVALID, "mu must be finite");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Units U = units();
+  const int nblk = 256;
+  // partials [nblk][36], then out [36], then kts [4]
+  EPH_HIP(c, c->sig_part.ensure(sizeof(double) * ((size_t)nblk * EPH_MAX_TEMPS * 9 + EPH_MAX_TEMPS * 9 + EPH_MAX_TEMPS)));
+  double *part = c->sig_part.as<double>();
+  double *outd = part + (size_t)nblk * EPH_MAX_TEMPS * 9;
+  double *kts = outd + EPH_MAX_TEMPS * 9;
+  double hk[EPH_MAX_TEMPS] = {1.0, 1.0, 1.0, 1.0};
+  for (int t = 0; t < n_temps; t++) hk[t] = U.kb_evk * temps_K[t];
+  EPH_HIP(c, hipMemcpyAsync(kts, hk, sizeof(hk), hipMemcpyHostToDevice, st));
+  const double pref = 2.0 * kCharge / ((double)n_kpoints * c->volume * 1e-30);
+  EPH_HIP(c, launch_sigma(n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, kts, pref, part, nblk, outd, st));
+  double ho[EPH_MAX_TEMPS * 9];
+  EPH_HIP(c, hipMemcpyAsync(ho, outd, sizeof(ho), hipMemcpyDeviceToHost, st));
+  EPH_HIP(c, hipStreamSynchronize(st));
+  for (int t = 0; t < n_temps; t++)
+    for (int q = 0; q < 9; q++) sigma_S_per_m[t * 9 + q] = ho[t * 9 + q];
+  return EPH_OK;
+}
+
+}  // extern "C"

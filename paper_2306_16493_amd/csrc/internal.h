@@ -1,0 +1,167 @@
+// Internal declarations of the gfx950 EPWI library: context layout, device
+// buffers and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "eph.h"
+
+namespace eph {
+
+// Exact SI 2019 constants (amu: CODATA 2022).
+constexpr double kPlanck = 6.62607015e-34;
+constexpr double kCharge = 1.602176634e-19;
+constexpr double kBoltz = 1.380649e-23;
+constexpr double kAmu = 1.66053906892e-27;
+constexpr double kPi = 3.14159265358979323846;
+
+struct Units {
+  double hbar_evs;   // hbar in eV s
+  double kb_evk;     // k_B in eV/K
+  double cph_ev;     // hbar^2/(amu A^2) in eV: (hbar w)^2 = cph * lambda
+  double vel_unit;   // (1 eV A)/hbar in m/s
+  double rate_pref;  // 2 pi / hbar in 1/(eV s)
+};
+Units units();
+
+// Grow-only device buffer.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf();
+  hipError_t ensure(size_t n);
+  template <class T>
+  T *as() const { return static_cast<T *>(p); }
+};
+
+struct RpBox {
+  int lo[3];
+  int n[3];
+  int count() const { return n[0] * n[1] * n[2]; }
+};
+
+}  // namespace eph
+
+struct eph_ctx {
+  int device = 0;
+  std::string err;
+  // model
+  int nw = 0, na = 0, nm = 0;
+  double lattice[9];
+  double volume = 0;  // A^3
+  std::vector<double> mode_mass;  // [nm]
+  int nrh = 0, nrd = 0, nre = 0, nrp = 0;
+  eph::RpBox box;
+  // device copies of the model
+  eph::DevBuf rh, rh_w, rh_cart, ham;   // ham: [nrh][nw*nw] double2
+  eph::DevBuf rd, rd_w, dyn;            // dyn: Phi/sqrt(MM') as double2 [nrd][nm*nm]
+  eph::DevBuf re;                       // [nre][3] int
+  eph::DevBuf wt64;                     // [nre*nw][box*nm*nw] double2 (K-major)
+  eph::DevBuf wt32;                     // same in float2 (lazy)
+  eph::DevBuf wtbf;                     // bf16 hi/lo split (lazy)
+  eph::DevBuf mode_mass_d;              // [nm]
+  // per-call workspaces (grow-only)
+  eph::DevBuf tab;                      // e^{2 pi i m/N}, [N] double2
+  eph::DevBuf eps, evec, vel, om, uu;   // grid tables
+  eph::DevBuf evec32, uu32;             // FP32 copies for reduced forms
+  eph::DevBuf cnt, offs, scan_tmp, subset;
+  eph::DevBuf grp_start, grp_tmp;
+  eph::DevBuf line_e, line_key;         // energy-sorted p-lines
+  eph::DevBuf xbuf;                     // X_s = Re transform + j rotation
+  eph::DevBuf counters;                 // int64 counters
+  eph::DevBuf sig_part;                 // sigma partial sums
+  eph::DevBuf state_cnt;                // per-state int64 counts
+  // stage timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;  // created on demand, reused across calls
+  int64_t launches[2] = {0, 0};
+  double stage_ms[5] = {0, 0, 0, 0, 0};
+  ~eph_ctx() {
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace eph {
+
+// ---- launchers (each returns the launch error) ----
+// Bloch sum + Hermitian eigensolve on grid points [k0, k0+nk).
+//  mode 0 (electrons): eval[k][n], evec[k][m][i] = V_im, vel[k][n][3] (m/s)
+//  mode 1 (phonons):   eval[k][nu] = hbar w (eV), evec[k][nu][mu] = u_{mu nu}
+//                      (A), zero for hbar w < omega_cut; counts excluded modes
+hipError_t launch_bloch_eig(int mode, int n, int N, int64_t k0, int64_t nk, int nr, const int *R,
+                            const double *w, const double *Rcart, const double2 *M, const double2 *tab,
+                            const double *mode_mass, double cph, double omega_cut, double vel_unit,
+                            double *eval, double2 *evec, double *vel, unsigned long long *n_excluded,
+                            hipStream_t st);
+hipError_t launch_phase_table(int N, double2 *tab, hipStream_t st);
+
+// State selection.  cnt/offs sized nklist+1.
+hipError_t launch_count_states(int64_t nklist, const int64_t *klist, int nw, const double *eps, int blo,
+                               int bhi, double wlo, double whi, int64_t *cnt, hipStream_t st);
+hipError_t launch_scan(int64_t n, const int64_t *in, int64_t *out_excl, int64_t *tmp, hipStream_t st);
+size_t scan_tmp_elems(int64_t n);
+hipError_t launch_write_states(int64_t nklist, const int64_t *klist, int nw, const double *eps,
+                               const double *vel, int blo, int bhi, double wlo, double whi,
+                               const int64_t *offs, int32_t *sk, int32_t *sn, double *se, double *sv,
+                               hipStream_t st);
+// Group heads: states of one k-line (same i2,i3), chunks of at most gmax.
+hipError_t launch_group_heads(int64_t ns, const int32_t *sk, int N, int gmax, int64_t *flag,
+                              hipStream_t st);
+hipError_t launch_group_starts(int64_t ns, const int64_t *flag, const int64_t *pos, int64_t *gstart,
+                               hipStream_t st);
+// Energy-sorted p-lines: for each line (i2,i3), entries key = i1*nw + m sorted by eps.
+hipError_t launch_line_sort(int N, int nw, const double *eps, double *line_e, uint16_t *line_key,
+                            hipStream_t st);
+
+// Re transform fused with the j->n rotation:
+//   X[s][rp][mu][i] = sum_{Re,j} Wt[(Re,j)][(rp,mu,i)] e^{i k_s.Re} V_{j n_s}(k_s)
+hipError_t launch_xform64(int64_t ns, const int32_t *sk, const int32_t *sn, int N, int nw, int nre,
+                          const int *re, int ncol, const double2 *wt, const double2 *evec,
+                          const double2 *tab, double2 *X, hipStream_t st);
+hipError_t launch_to_f32(int64_t n, const double2 *in, float2 *out, hipStream_t st);
+
+struct RatesArgs {
+  int N, nw, nm, nt;
+  RpBox box;
+  double mu, eta, sw, wcut, wmax;
+  double temps_kt[EPH_MAX_TEMPS];  // k_B T in eV
+  double pref;                     // 2 pi / hbar / N^3
+  int64_t ng;                      // groups in this launch
+  const int64_t *gstart;           // [ng+1] absolute state indices
+  int64_t s_base;                  // state index of X row 0
+  const int32_t *sk, *sn;
+  const double *eps;               // [N^3][nw]
+  const double *om;                // [N^3][nm]
+  const double2 *evec;             // [N^3][nw][nw]
+  const double2 *uu;               // [N^3][nm][nm]
+  const float2 *evec32, *uu32;
+  const double *line_e;
+  const uint16_t *line_key;
+  const double2 *tab;
+  const void *X;                   // [ns][box][nm*nw] double2 or float2
+  double *inv_tau;                 // [nt][ns_total]
+  int64_t ns_total;
+  int64_t *st_counts;              // [ns_total][2]: n_q_valid, n_terms
+  unsigned long long *n_kq;
+  unsigned long long *n_vertex;
+};
+hipError_t launch_rates(int precision, const RatesArgs &a, hipStream_t st);
+
+// sigma partial sums per block, then out[T*9 + ab] = pref * sum of partials
+// (partials: [nblk][EPH_MAX_TEMPS*9], out: [EPH_MAX_TEMPS*9], kts: device [nt]).
+hipError_t launch_sigma(int64_t ns, const double *e, const double *v, const double *inv_tau, double mu,
+                        int nt, const double *kts, double pref, double *partials, int nblk, double *out,
+                        hipStream_t st);
+int rates_group_max(int nw, int nm);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_max_nonneg(int64_t n, const double *x, unsigned long long *out, hipStream_t st);
+hipError_t launch_summarize(int64_t ns, const int64_t *st_counts, const double *inv_tau0,
+                            unsigned long long *out, hipStream_t st);
+size_t rates_smem_bytes(int precision, int N, int nw, int nm, RpBox box);
+
+}  // namespace eph

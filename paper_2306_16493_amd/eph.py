@@ -1,0 +1,235 @@
+"""Python binding of the gfx950 EPWI library (argument marshalling only).
+
+Every step of the computation runs in the HIP kernels of ``libeph.so``; this
+module converts numpy model arrays to the C structs of ``include/eph.h`` and
+passes torch device buffers (for memory and streams) through the C ABI.  If
+the library is missing it raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeph.so")
+
+EPH_OK, EPH_E_INVALID, EPH_E_NOMEM, EPH_E_DEVICE, EPH_E_STATE, EPH_E_TRUNCATED, EPH_E_UNSUPPORTED = range(7)
+EPH_FP64, EPH_FP32, EPH_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": EPH_FP64, "fp32": EPH_FP32, "bf16x3": EPH_BF16X3}
+MAX_TEMPS = 4
+
+# every symbol declared in include/eph.h
+EXPORTS = ("eph_load_wannier", "eph_free", "eph_last_error", "eph_scattering_rates", "eph_conductivity",
+           "eph_set_profiling", "eph_stage_times")
+
+
+class EphError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"eph status {code}: {msg}")
+        self.code = code
+
+
+class Model(C.Structure):
+    _fields_ = [("lattice", C.c_double * 9), ("n_atoms", C.c_int32), ("mass_amu", C.c_void_p),
+                ("n_wann", C.c_int32), ("n_rh", C.c_int32), ("rh", C.c_void_p), ("rh_w", C.c_void_p),
+                ("ham", C.c_void_p), ("n_rd", C.c_int32), ("rd", C.c_void_p), ("rd_w", C.c_void_p),
+                ("ifc", C.c_void_p), ("n_re", C.c_int32), ("re", C.c_void_p), ("n_rp", C.c_int32),
+                ("rp", C.c_void_p), ("gw", C.c_void_p)]
+
+
+class RatesParams(C.Structure):
+    _fields_ = [("grid", C.c_int32 * 3), ("mu_eV", C.c_double), ("n_temps", C.c_int32),
+                ("temps_K", C.c_void_p), ("eta_eV", C.c_double), ("sieve_width", C.c_double),
+                ("win_lo_eV", C.c_double), ("win_hi_eV", C.c_double), ("band_lo", C.c_int32),
+                ("band_hi", C.c_int32), ("omega_cut_eV", C.c_double), ("precision", C.c_int32),
+                ("k_subset", C.c_void_p), ("n_k_subset", C.c_int64), ("stream", C.c_void_p)]
+
+
+class Counts(C.Structure):
+    _fields_ = [("n_states", C.c_int64), ("n_kq", C.c_int64), ("n_nkq", C.c_int64), ("n_terms", C.c_int64),
+                ("n_zero_rate", C.c_int64), ("n_excluded_modes", C.c_int64), ("n_vertex", C.c_int64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libeph.so (built in-tree by build.py); raise if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2306_16493_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        L.eph_load_wannier.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(C.c_void_p)]
+        L.eph_load_wannier.restype = C.c_int32
+        L.eph_free.argtypes = [C.c_void_p]
+        L.eph_free.restype = None
+        L.eph_last_error.argtypes = [C.c_void_p]
+        L.eph_last_error.restype = C.c_char_p
+        L.eph_scattering_rates.argtypes = [C.c_void_p, C.POINTER(RatesParams), C.c_int64, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Counts)]
+        L.eph_scattering_rates.restype = C.c_int32
+        L.eph_conductivity.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                       C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.eph_conductivity.restype = C.c_int32
+        L.eph_set_profiling.argtypes = [C.c_void_p, C.c_int32]
+        L.eph_set_profiling.restype = C.c_int32
+        L.eph_stage_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.eph_stage_times.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+@dataclass
+class RatesResult:
+    state_k: "object"      # torch int32 [ns] on the device
+    state_n: "object"
+    energy: "object"       # float64 [ns]
+    vel: "object"          # float64 [ns][3]
+    inv_tau: "object"      # float64 [nt][ns]
+    counts: dict
+
+
+class Context:
+    """An eph_ctx: the Wannier model resident on one GPU."""
+
+    def __init__(self, system, device: int = 0):
+        L = lib()
+        self._keep = dict(
+            mass=np.ascontiguousarray(system.mass, np.float64),
+            rh=np.ascontiguousarray(system.rh, np.int32), rh_w=np.ascontiguousarray(system.rh_w, np.float64),
+            ham=np.ascontiguousarray(system.ham, np.complex128),
+            rd=np.ascontiguousarray(system.rd, np.int32), rd_w=np.ascontiguousarray(system.rd_w, np.float64),
+            ifc=np.ascontiguousarray(system.ifc, np.float64),
+            re=np.ascontiguousarray(system.re, np.int32), rp=np.ascontiguousarray(system.rp, np.int32),
+            gw=np.ascontiguousarray(system.gw, np.complex128))
+        k = self._keep
+        m = Model()
+        for i, v in enumerate(np.asarray(system.lattice, np.float64).ravel()):
+            m.lattice[i] = float(v)
+        m.n_atoms = k["mass"].shape[0]
+        m.mass_amu = _ptr(k["mass"])
+        m.n_wann = int(system.nw)
+        m.n_rh, m.rh, m.rh_w, m.ham = k["rh"].shape[0], _ptr(k["rh"]), _ptr(k["rh_w"]), _ptr(k["ham"])
+        m.n_rd, m.rd, m.rd_w, m.ifc = k["rd"].shape[0], _ptr(k["rd"]), _ptr(k["rd_w"]), _ptr(k["ifc"])
+        m.n_re, m.re, m.n_rp, m.rp, m.gw = k["re"].shape[0], _ptr(k["re"]), k["rp"].shape[0], _ptr(k["rp"]), \
+            _ptr(k["gw"])
+        self._model = m
+        h = C.c_void_p()
+        st = L.eph_load_wannier(C.byref(m), int(device), C.byref(h))
+        if st != EPH_OK:
+            raise EphError(st, L.eph_last_error(None).decode())
+        self._h = h
+        self.device = device
+        self.nw = int(system.nw)
+        self.nm = 3 * k["mass"].shape[0]
+        del self._keep["gw"]  # copied to the device; the host copy is not needed any more
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().eph_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def last_error(self):
+        return lib().eph_last_error(self._h).decode()
+
+    def _check(self, st, allow=()):
+        if st != EPH_OK and st not in allow:
+            raise EphError(st, self.last_error())
+        return st
+
+    @staticmethod
+    def params(grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, sieve_width=6.0,
+               omega_cut=1e-4, precision="fp64", k_subset=None, stream=None):
+        p = RatesParams()
+        p.grid[0] = p.grid[1] = p.grid[2] = int(grid)
+        p.mu_eV = float(mu)
+        temps = np.ascontiguousarray(np.atleast_1d(temps), np.float64)
+        p.n_temps = temps.shape[0]
+        p.temps_K = _ptr(temps)
+        p.eta_eV, p.sieve_width = float(eta), float(sieve_width)
+        p.win_lo_eV, p.win_hi_eV = float(win_lo), float(win_hi)
+        p.band_lo, p.band_hi = int(band_lo), int(band_hi)
+        p.omega_cut_eV = float(omega_cut)
+        p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        keep = [temps]
+        if k_subset is not None:
+            ks = np.ascontiguousarray(k_subset, np.int64)
+            n = ks.shape[0]
+            if n == 0:
+                ks = np.zeros(1, np.int64)  # a valid pointer with zero entries
+            keep.append(ks)
+            p.k_subset, p.n_k_subset = _ptr(ks), n
+        else:
+            p.k_subset, p.n_k_subset = None, 0
+        p.stream = C.c_void_p(stream) if stream else None
+        p._keep = keep
+        return p
+
+    def count_states(self, params) -> int:
+        cnt = Counts()
+        st = lib().eph_scattering_rates(self._h, C.byref(params), 0, None, None, None, None, None, C.byref(cnt))
+        self._check(st, allow=(EPH_E_TRUNCATED,))
+        return int(cnt.n_states)
+
+    def scattering_rates(self, params, capacity: Optional[int] = None, buffers=None) -> RatesResult:
+        """Run eph_scattering_rates into torch device buffers (allocated here
+        unless given as a dict from a previous result)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if capacity is None:
+            capacity = self.count_states(params)
+        nt = int(params.n_temps)
+        cap = max(int(capacity), 1)
+        if buffers is None:
+            buffers = dict(k=torch.empty(cap, dtype=torch.int32, device=dev),
+                           n=torch.empty(cap, dtype=torch.int32, device=dev),
+                           e=torch.empty(cap, dtype=torch.float64, device=dev),
+                           v=torch.empty(cap, 3, dtype=torch.float64, device=dev),
+                           it=torch.empty(nt * cap, dtype=torch.float64, device=dev))
+        cnt = Counts()
+        st = lib().eph_scattering_rates(self._h, C.byref(params), int(capacity), _dptr(buffers["k"]),
+                                        _dptr(buffers["n"]), _dptr(buffers["e"]), _dptr(buffers["v"]),
+                                        _dptr(buffers["it"]), C.byref(cnt))
+        self._check(st)
+        ns = int(cnt.n_states)
+        return RatesResult(buffers["k"][:ns], buffers["n"][:ns], buffers["e"][:ns], buffers["v"][:ns],
+                           buffers["it"][:nt * ns].view(nt, ns), cnt.as_dict()), buffers
+
+    def set_profiling(self, on=True):
+        self._check(lib().eph_set_profiling(self._h, 1 if on else 0))
+
+    def stage_times(self):
+        ms = np.zeros(5)
+        ln = np.zeros(2, np.int64)
+        self._check(lib().eph_stage_times(self._h, _ptr(ms), _ptr(ln)))
+        return dict(tables_ms=ms[0], prep_ms=ms[1], xform_ms=ms[2], rates_ms=ms[3], call_ms=ms[4],
+                    xform_launches=int(ln[0]), rates_launches=int(ln[1]))
+
+    def conductivity(self, energy, vel, inv_tau, mu, temps, n_kpoints, stream=None):
+        temps = np.ascontiguousarray(np.atleast_1d(temps), np.float64)
+        out = np.zeros((temps.shape[0], 3, 3))
+        ns = int(energy.shape[0])
+        st = lib().eph_conductivity(self._h, ns, _dptr(energy.contiguous()), _dptr(vel.contiguous()),
+                                    _dptr(inv_tau.contiguous()), float(mu), temps.shape[0], _ptr(temps),
+                                    int(n_kpoints), C.c_void_p(stream) if stream else None, _ptr(out))
+        self._check(st)
+        return out

@@ -1,0 +1,195 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (FP64 path): energies and velocities 1e-10 of the largest value;
+1/tau 1e-10 relative per state (states in near-degenerate pairs compared by
+group sums); sigma 1e-10 relative to its largest element; integer counts
+exact.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import log, params_for, gpu_run, degenerate_mask, rel_err
+from synth import make_system, workload
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def compare_rates(g, o_inv, eps_table, sk, sn, tol=TOL):
+    deg = degenerate_mask(eps_table, sk, sn)
+    it_g, it_o = g["inv_tau"], o_inv
+    scale = np.max(np.abs(it_o))
+    for t in range(it_o.shape[0]):
+        a, b = it_g[t][~deg], it_o[t][~deg]
+        err = np.abs(a - b) / np.maximum(np.abs(b), 1e-12 * scale)
+        log(f"  T{t}: max rel err 1/tau = {err.max() if err.size else 0:.3e} over {err.size} states "
+            f"({deg.sum()} near-degenerate)")
+        assert err.size == 0 or err.max() < tol
+        if deg.any():
+            # near-degenerate states: compare sums over the degenerate set at each k
+            for k in np.unique(sk[deg]):
+                sel = (sk == k) & deg
+                assert abs(it_g[t][sel].sum() - it_o[t][sel].sum()) <= tol * max(abs(it_o[t][sel].sum()),
+                                                                                 1e-12 * scale)
+
+
+def full_parity(torch, name, grid=None, temps=None, window=None, k_subset=None):
+    from paper_2306_16493_amd import Context
+    w = workload(name, grid)
+    s = make_system(w.system)
+    ctx = Context(s)
+    p, (N, mu, lo, hi) = params_for(ctx, w, s, grid, k_subset=k_subset, temps=temps, window=window)
+    log(f"[parity] {name} N={N} window=({lo:.4f},{hi:.4f}) subset={None if k_subset is None else len(k_subset)}")
+    g = gpu_run(ctx, p)
+    o = Oracle(s)
+    r = o.run(N, mu, temps or w.temps, w.eta, lo, hi, w.band_lo, w.band_hi, k_subset=k_subset)
+    assert np.array_equal(g["state_k"], r["state_k"])
+    assert np.array_equal(g["state_n"], r["state_n"])
+    assert rel_err(g["energy"], r["energy"]) < TOL
+    assert np.max(np.abs(g["vel"] - r["vel"])) <= TOL * max(np.abs(r["vel"]).max(), 1.0)
+    eps_table = r["tables"][0]
+    if len(r["state_k"]):
+        compare_rates(g, r["inv_tau"], eps_table, r["state_k"], r["state_n"])
+    c = g["counts"]
+    assert c["n_states"] == len(r["state_k"])
+    assert c["n_kq"] == r["n_kq"]
+    assert c["n_nkq"] == int(r["n_q_valid"].sum())
+    assert c["n_terms"] == int(r["n_terms"].sum())
+    # sigma through the ABI (device inputs) vs the oracle's reduction
+    if len(r["state_k"]):
+        res = g["res"]
+        sig_g = ctx.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, temps or w.temps, N ** 3)
+        assert rel_err(sig_g, r["sigma"]) < TOL
+    ctx.close()
+    return g, r
+
+
+def test_toy_sc_8_full(torch_cuda):
+    """8^3 k x 8^3 q simple-cubic toy: every (n,k) state, every q."""
+    g, r = full_parity(torch_cuda, "toy_sc_8")
+    assert g["counts"]["n_states"] == 2048
+
+
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_toy_odd_grids(torch_cuda, N):
+    full_parity(torch_cuda, "toy_sc_8", grid=N)
+
+
+def test_al_fcc_small_three_temperatures(torch_cuda):
+    """Al-like metal on 12^3 with the 100/300/500 K batch in one pass."""
+    full_parity(torch_cuda, "al_fcc_100", grid=12)
+
+
+def test_si_fcc_small_two_atoms(torch_cuda):
+    """Si-like 2-atom system (8 orbitals, 6 modes) on 6^3, conduction bands."""
+    w = workload("si_fcc_150", 6)
+    s = make_system("si_fcc")
+    eps, _, _ = Oracle(s).electrons(6)
+    cbm = eps[:, 4].min()
+    # window edges kept off state energies (the CBM itself is a state)
+    full_parity(torch_cuda, "si_fcc_150", grid=6, window=(cbm - 1e-7, cbm + 0.4))
+
+
+def test_k_subset_and_empty_cases(torch_cuda):
+    rng = np.random.default_rng(4)
+    ks = rng.choice(8 ** 3, size=23, replace=False)
+    ks = np.concatenate([ks, ks[:5]])  # duplicates are ignored
+    full_parity(torch_cuda, "toy_sc_8", k_subset=ks)
+    from paper_2306_16493_amd import Context
+    s = make_system("toy_sc")
+    ctx = Context(s)
+    w = workload("toy_sc_8")
+    p, _ = params_for(ctx, w, s, k_subset=np.zeros(0, np.int64))
+    g = gpu_run(ctx, p)
+    assert g["counts"]["n_states"] == 0 and g["inv_tau"].size == 0
+    p, _ = params_for(ctx, w, s, window=(50.0, 60.0))
+    g = gpu_run(ctx, p)
+    assert g["counts"]["n_states"] == 0
+
+
+def test_truncation_reports_count(torch_cuda):
+    from paper_2306_16493_amd import Context, EphError
+    from paper_2306_16493_amd.eph import EPH_E_TRUNCATED
+    s = make_system("toy_sc")
+    ctx = Context(s)
+    p, _ = params_for(ctx, workload("toy_sc_8"), s, grid=4)
+    n = ctx.count_states(p)
+    assert n == 4 ** 3 * 4
+    with pytest.raises(EphError) as ei:
+        ctx.scattering_rates(p, capacity=n - 1)
+    assert ei.value.code == EPH_E_TRUNCATED
+
+
+def test_bitwise_deterministic(torch_cuda):
+    from paper_2306_16493_amd import Context
+    s = make_system("al_fcc")
+    ctx = Context(s)
+    p, (N, mu, _, _) = params_for(ctx, workload("al_fcc_100", 10), s, grid=10)
+    a = gpu_run(ctx, p)
+    b = gpu_run(ctx, p)
+    assert np.array_equal(a["inv_tau"], b["inv_tau"])
+    sa = ctx.conductivity(a["res"].energy, a["res"].vel, a["res"].inv_tau.reshape(-1), mu, [300.0], N ** 3)
+    sb = ctx.conductivity(a["res"].energy, a["res"].vel, a["res"].inv_tau.reshape(-1), mu, [300.0], N ** 3)
+    assert np.array_equal(sa, sb)
+
+
+def test_conductivity_constant_tau(torch_cuda):
+    """sigma of a constant-tau input equals the oracle's reduction."""
+    import torch
+    from paper_2306_16493_amd import Context
+    s = make_system("al_fcc")
+    ctx = Context(s)
+    rng = np.random.default_rng(2)
+    ns = 100003
+    e = rng.normal(s.mu_centroid, 0.1, ns)
+    v = rng.normal(0, 1e6, (ns, 3))
+    inv = np.full((2, ns), 1e13)
+    dev = torch.device("cuda")
+    sig = ctx.conductivity(torch.tensor(e, device=dev), torch.tensor(v, device=dev),
+                           torch.tensor(inv.reshape(-1), device=dev), s.mu_centroid, [200.0, 400.0], 10 ** 6)
+    ref = Oracle(s).sigma(e, v, inv, s.mu_centroid, [200.0, 400.0], 10 ** 6)
+    assert rel_err(sig, ref) < 1e-12
+
+
+def test_al_fcc_100_full_size_sampled(torch_cuda):
+    """The benchmarked configuration (Al-like, 100^3 k x 100^3 q, 3
+    temperatures, |e - mu| < 0.3 eV) run whole on the GPU; a seeded sample of
+    states is recomputed one by one by the oracle."""
+    from paper_2306_16493_amd import Context
+    w = workload("al_fcc_100")
+    s = make_system(w.system)
+    ctx = Context(s)
+    p, (N, mu, lo, hi) = params_for(ctx, w, s)
+    log(f"[parity] al_fcc_100 full run on the GPU")
+    g = gpu_run(ctx, p)
+    ns = g["counts"]["n_states"]
+    log(f"  states={ns} counts={g['counts']}")
+    rng = np.random.default_rng(1649302 + 7)
+    pick = np.sort(rng.choice(ns, size=6, replace=False))
+    kpick = np.unique(g["state_k"][pick])
+    o = Oracle(s)
+    log("  oracle tables ...")
+    eps, evec, vel = o.electrons(N)
+    om, u, _ = o.phonons(N)
+    sk, sn = o.select_states(eps, w.band_lo, w.band_hi, lo, hi, k_subset=kpick)
+    log(f"  oracle rates for {len(sk)} states at {len(kpick)} k points ...")
+    r = o.rates(N, eps, evec, om, u, sk, sn, mu, w.temps, w.eta)
+    # map oracle states into the GPU list
+    idx = {(int(k), int(n)): i for i, (k, n) in enumerate(zip(g["state_k"], g["state_n"]))}
+    gi = np.array([idx[(int(k), int(n))] for k, n in zip(sk, sn)])
+    sub = dict(inv_tau=g["inv_tau"][:, gi])
+    compare_rates(sub, r["inv_tau"], eps, sk, sn)
+    assert np.max(np.abs(g["energy"][gi] - eps[sk, sn])) < TOL * np.abs(eps).max()
+    # the full-grid state count is a property of the whole run
+    sk_all, _ = o.select_states(eps, w.band_lo, w.band_hi, lo, hi)
+    assert len(sk_all) == ns
