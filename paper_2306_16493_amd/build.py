@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libeph.so")
 
 
-def hipcc_command(out=LIB, arch="gfx950", debug=False):
+def hipcc_command(out=LIB, arch="gfx950", debug=False, defines=()):
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
     cmd = ["/opt/rocm/bin/hipcc", "-shared", "-fPIC", "-std=c++17", "-O3",
            "--offload-arch=" + arch,
@@ -19,18 +19,20 @@ def hipcc_command(out=LIB, arch="gfx950", debug=False):
            "-o", out] + srcs
     if debug:
         cmd.insert(1, "-g")
+    for d in defines:
+        cmd.insert(1, "-D" + d)
     return cmd
 
 
-def build(verbose=False):
-    cmd = hipcc_command()
+def build(verbose=False, out=LIB, defines=()):
+    cmd = hipcc_command(out=out, defines=defines)
     if verbose:
         print(" ".join(cmd), flush=True)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd[cmd.index("-o") + 1] = tmp
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

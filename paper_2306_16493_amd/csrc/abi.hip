@@ -1,6 +1,7 @@
 // C ABI of the gfx950 EPWI transport library: model validation and upload,
 // orchestration of the kernels of one scattering-rates call, conductivity.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -292,7 +293,7 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
     return fail(c, EPH_E_INVALID, "mu / window must be numbers");
   if (p->precision != EPH_FP64 && p->precision != EPH_FP32 && p->precision != EPH_BF16X3)
     return fail(c, EPH_E_INVALID, "unknown precision");
-  if (p->precision != EPH_FP64) return fail(c, EPH_E_UNSUPPORTED, "reduced-precision forms not built");
+  if (p->precision == EPH_BF16X3) return fail(c, EPH_E_UNSUPPORTED, "BF16x3 form not built");
   const int blo = p->band_lo, bhi = p->band_hi < 0 ? c->nw - 1 : p->band_hi;
   if (blo < 0 || blo > bhi || bhi >= c->nw) return fail(c, EPH_E_INVALID, "band range outside 0..n_wann-1");
   if (capacity < 0) return fail(c, EPH_E_INVALID, "capacity < 0");
@@ -339,6 +340,18 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
                               c->dyn.as<double2>(), c->tab.as<double2>(), c->mode_mass_d.as<double>(), U.cph_ev,
                               p->omega_cut_eV, U.vel_unit, c->om.as<double>(), c->uu.as<double2>(), nullptr, ctr + 0,
                               st));
+  const bool fp32 = p->precision != EPH_FP64;
+  if (fp32) {  // FP32 copies of the rotation tables for the reduced-precision forms
+    EPH_HIP(c, c->evec32.ensure(sizeof(float2) * NQ * nw * nw));
+    EPH_HIP(c, c->uu32.ensure(sizeof(float2) * NQ * nm * nm));
+    EPH_HIP(c, launch_to_f32(NQ * nw * nw, c->evec.as<double2>(), c->evec32.as<float2>(), st));
+    EPH_HIP(c, launch_to_f32(NQ * nm * nm, c->uu.as<double2>(), c->uu32.as<float2>(), st));
+    const size_t nwt = (size_t)c->nre * nw * c->box.count() * nm * nw;
+    if (c->wt32.bytes < sizeof(float2) * nwt) {
+      EPH_HIP(c, c->wt32.ensure(sizeof(float2) * nwt));
+      EPH_HIP(c, launch_to_f32((int64_t)nwt, c->wt64.as<double2>(), c->wt32.as<float2>(), st));
+    }
+  }
   EPH_HIP(c, tm.mark(&e_tables));
 
   // ---- states in the window ----
@@ -371,7 +384,16 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
 
   if (ns > 0) {
     // ---- groups of states sharing a k-line ----
-    const int gmax = rates_group_max(nw, nm);
+    // kernel choice: staged q-line form, else wave-autonomous, else workgroup form
+    // EPH_RATES_KERNEL=stage|wave|group selects a form (for measurements); the
+    // default is the wave-autonomous form where it applies
+    const char *kc = std::getenv("EPH_RATES_KERNEL");
+    const std::string ks = kc ? kc : "";
+    const bool allow_stage = ks == "stage", allow_wave = ks.empty() || ks == "wave";
+    const int gstage =
+        (allow_stage && p->precision == EPH_FP64) ? rates_stage_group(nw, nm, c->box, N, p->n_temps) : 0;
+    const int gwave = (gstage > 0 || !allow_wave) ? 0 : rates_wave_group(nw, nm, c->box, N);
+    const int gmax = gstage > 0 ? gstage : gwave > 0 ? gwave : rates_group_max(nw, nm);
     EPH_HIP(c, c->grp_tmp.ensure(sizeof(int64_t) * 2 * (ns + 1)));
     int64_t *flag = c->grp_tmp.as<int64_t>(), *pos = flag + ns + 1;
     EPH_HIP(c, c->scan_tmp.ensure(sizeof(int64_t) * std::max(scan_tmp_elems(nkl + 1), scan_tmp_elems(ns))));
@@ -389,9 +411,26 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
     EPH_HIP(c, hipMemcpyAsync(hg.data(), gstart, sizeof(int64_t) * (ng + 1), hipMemcpyDeviceToHost, st));
 
     // ---- energy-sorted final-state lines; largest phonon energy ----
-    EPH_HIP(c, c->line_e.ensure(sizeof(double) * NQ * nw));
-    EPH_HIP(c, c->line_key.ensure(sizeof(uint16_t) * NQ * nw));
-    EPH_HIP(c, launch_line_sort(N, nw, c->eps.as<double>(), c->line_e.as<double>(), c->line_key.as<uint16_t>(), st));
+    if (gwave == 0 && gstage == 0) {
+      EPH_HIP(c, c->line_e.ensure(sizeof(double) * NQ * nw));
+      EPH_HIP(c, c->line_key.ensure(sizeof(uint16_t) * NQ * nw));
+      EPH_HIP(c, launch_line_sort(N, nw, c->eps.as<double>(), c->line_e.as<double>(), c->line_key.as<uint16_t>(),
+                                  st));
+    } else {
+      double kts[EPH_MAX_TEMPS];
+      for (int t = 0; t < p->n_temps; t++) kts[t] = U.kb_evk * p->temps_K[t];
+      EPH_HIP(c, c->occ.ensure(sizeof(double) * NQ * (nw + nm) * p->n_temps));
+      EPH_HIP(c, launch_occupations(NQ, nw, nm, c->eps.as<double>(), c->om.as<double>(), p->mu_eV, p->n_temps, kts,
+                                    p->omega_cut_eV, c->occ.as<double>(),
+                                    c->occ.as<double>() + (size_t)NQ * nw * p->n_temps, st));
+      if (gstage > 0) {
+        EPH_HIP(c, c->packed.ensure(sizeof(double) * stage_table_words(NQ, nw, nm, p->n_temps)));
+        EPH_HIP(c, launch_pack_tables(NQ, nw, nm, p->n_temps, c->eps.as<double>(), c->om.as<double>(),
+                                      c->evec.as<double2>(), c->uu.as<double2>(), c->occ.as<double>(),
+                                      c->occ.as<double>() + (size_t)NQ * nw * p->n_temps, c->packed.as<double>(),
+                                      c->packed.as<double>() + stage_table_words(NQ, 0, nm, p->n_temps), st));
+      }
+    }
     EPH_HIP(c, launch_max_nonneg(NQ * nm, c->om.as<double>(), ctr + 1, st));
     EPH_HIP(c, tm.mark(&e_prep));
     unsigned long long wbits = 0;
@@ -401,7 +440,7 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
     std::memcpy(&wmax, &wbits, sizeof(wmax));
 
     // ---- per batch of groups: Re transform, then the fused rate kernel ----
-    const size_t xrow = (size_t)c->box.count() * nm * nw * sizeof(double2);
+    const size_t xrow = (size_t)c->box.count() * nm * nw * (fp32 ? sizeof(float2) : sizeof(double2));
     const size_t budget = (size_t)8 << 30;
     int64_t max_states = std::max<int64_t>(gmax, (int64_t)(budget / xrow));
     EPH_HIP(c, c->state_cnt.ensure(sizeof(int64_t) * 2 * ns));
@@ -433,6 +472,10 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
     a.st_counts = c->state_cnt.as<int64_t>();
     a.n_kq = ctr + 2;
     a.n_vertex = ctr + 6;
+    a.evec32 = fp32 ? c->evec32.as<float2>() : nullptr;
+    a.uu32 = fp32 ? c->uu32.as<float2>() : nullptr;
+    a.occ_f = c->occ.as<double>();
+    a.occ_n = c->occ.as<double>() + (size_t)NQ * nw * p->n_temps;
     const int ncol = c->box.count() * nm * nw;
     int64_t g0 = 0;
     while (g0 < ng) {
@@ -442,15 +485,33 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
       EPH_HIP(c, c->xbuf.ensure(xrow * (size_t)(sb - sa)));
       int eb0, eb1, eb2;
       EPH_HIP(c, tm.mark(&eb0));
-      EPH_HIP(c, launch_xform64(sb - sa, state_k + sa, state_n + sa, N, nw, c->nre, c->re.as<int>(), ncol,
-                                c->wt64.as<double2>(), c->evec.as<double2>(), c->tab.as<double2>(),
-                                c->xbuf.as<double2>(), st));
+      if (fp32)
+        EPH_HIP(c, launch_xform32(sb - sa, state_k + sa, state_n + sa, N, nw, c->nre, c->re.as<int>(), ncol,
+                                  c->wt32.as<float2>(), c->evec.as<double2>(), c->tab.as<double2>(),
+                                  c->xbuf.as<float2>(), st));
+      else
+        EPH_HIP(c, launch_xform64(sb - sa, state_k + sa, state_n + sa, N, nw, c->nre, c->re.as<int>(), ncol,
+                                  c->wt64.as<double2>(), c->evec.as<double2>(), c->tab.as<double2>(),
+                                  c->xbuf.as<double2>(), st));
       a.ng = g1 - g0;
       a.gstart = gstart + g0;
       a.s_base = sa;
       a.X = c->xbuf.p;
       EPH_HIP(c, tm.mark(&eb1));
-      EPH_HIP(c, launch_rates(EPH_FP64, a, st));
+      if (gstage > 0)
+        EPH_HIP(c, launch_rates_stage(a, c->packed.as<double>(),
+                                      c->packed.as<double>() + stage_table_words(NQ, 0, nm, p->n_temps), st));
+      else if (gwave > 0) {
+        // one launch per q3 plane: every resident wave then works on the same
+        // plane, whose q-side tables stay in the XCD's L2
+        for (int q3 = 0; q3 < N; q3++) {
+          a.q3_lo = q3;
+          a.q3_hi = q3 + 1;
+          a.q3_cur = q3;
+          EPH_HIP(c, launch_rates_wave(p->precision, a, st));
+        }
+      } else
+        EPH_HIP(c, launch_rates(p->precision, a, st));
       EPH_HIP(c, tm.mark(&eb2));
       e_batch.insert(e_batch.end(), {eb0, eb1, eb2});
       c->launches[0]++;

@@ -75,6 +75,8 @@ struct eph_ctx {
   eph::DevBuf counters;                 // int64 counters
   eph::DevBuf sig_part;                 // sigma partial sums
   eph::DevBuf state_cnt;                // per-state int64 counts
+  eph::DevBuf occ;                      // Fermi and Bose factor tables
+  eph::DevBuf packed;                   // packed q-side / p-side records
   // stage timing
   bool profiling = false;
   std::vector<hipEvent_t> ev;  // created on demand, reused across calls
@@ -123,6 +125,9 @@ hipError_t launch_line_sort(int N, int nw, const double *eps, double *line_e, ui
 hipError_t launch_xform64(int64_t ns, const int32_t *sk, const int32_t *sn, int N, int nw, int nre,
                           const int *re, int ncol, const double2 *wt, const double2 *evec,
                           const double2 *tab, double2 *X, hipStream_t st);
+hipError_t launch_xform32(int64_t ns, const int32_t *sk, const int32_t *sn, int N, int nw, int nre,
+                          const int *re, int ncol, const float2 *wt, const double2 *evec,
+                          const double2 *tab, float2 *X, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double2 *in, float2 *out, hipStream_t st);
 
 struct RatesArgs {
@@ -149,8 +154,28 @@ struct RatesArgs {
   int64_t *st_counts;              // [ns_total][2]: n_q_valid, n_terms
   unsigned long long *n_kq;
   unsigned long long *n_vertex;
+  const double *occ_f;             // [N^3][nw][nt] Fermi factors (wave kernel)
+  const double *occ_n;             // [N^3][nm][nt] Bose factors, 0 below omega_cut
+  int q3_lo, q3_hi;                // q3 planes of this launch (wave kernel)
+  int q3_cur;                      // the plane (wave kernel launches one plane at a time)
 };
 hipError_t launch_rates(int precision, const RatesArgs &a, hipStream_t st);
+// Wave-autonomous rate kernel; rates_wave_group gives its states per group
+// (0 when the shape is not served and launch_rates must be used).
+int rates_wave_group(int nw, int nm, RpBox box, int N);
+hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st);
+// Staged q-line rate kernel (FP64): states per group, 0 when not served.
+int rates_stage_group(int nw, int nm, RpBox box, int N, int nt);
+size_t stage_table_words(int64_t nq, int nw, int nm, int nt);
+hipError_t launch_pack_tables(int64_t nq, int nw, int nm, int nt, const double *eps, const double *om,
+                              const double2 *evec, const double2 *uu, const double *occ_f, const double *occ_n,
+                              double *qt, double *pt, hipStream_t st);
+hipError_t launch_rates_stage(const RatesArgs &a, const double *qt, const double *pt, hipStream_t st);
+// Occupation tables: occ_f[k][n][t] = 1/(exp((eps-mu)/kT_t)+1),
+// occ_n[q][nu][t] = 1/expm1(hbar w/kT_t) (0 when hbar w < wcut).
+hipError_t launch_occupations(int64_t nq, int nw, int nm, const double *eps, const double *om, double mu,
+                              int nt, const double *kts_host, double wcut, double *occ_f, double *occ_n,
+                              hipStream_t st);
 
 // sigma partial sums per block, then out[T*9 + ab] = pref * sum of partials
 // (partials: [nblk][EPH_MAX_TEMPS*9], out: [EPH_MAX_TEMPS*9], kts: device [nt]).

@@ -1,0 +1,492 @@
+// SERTA scattering rates, wave-autonomous form (gfx950).
+//
+// Same arithmetic as the workgroup form (separable Rp box: Y per q3, Z per
+// q-line, G per q; vertex contracted onto the final band m first, then onto
+// the modes; sieve, occupations, Gaussian delta; Sec. II.B/II.C/III.A/III.C),
+// organised so that no workgroup barrier sits inside the q loops:
+//   * each wave64 owns a group of <= GW initial states on one k-line and
+//     sweeps all q-lines on its own; the four waves of a workgroup take
+//     consecutive groups of the same k-line, so their table reads share L1;
+//   * Y_s(p1,p2; q3) lives in registers, one (state, p1, channel) pair per
+//     lane slot, so Z_s(p1; q2,q3) is a lane-local 1-D transform whose
+//     result goes to the wave's LDS slice;
+//   * the final-state line p = k + q (contiguous in the energy table) is
+//     scanned 64 entries at a time; entries within max(hbar w) + sw*eta of a
+//     state's energy are compacted with ballots into an LDS queue, and the
+//     queue is drained in full passes of 64 lanes;
+//   * Fermi and Bose factors come from per-call grid tables, so a candidate
+//     pays one exp per kept term (the delta) and no other transcendental;
+//   * phases use 32-bit indices advanced incrementally (no 64-bit modulo).
+// Per-state rates are accumulated per lane and reduced with a fixed
+// butterfly at the end, so results are bit-reproducible.
+#include "dev_util.h"
+#include "internal.h"
+
+namespace eph {
+namespace {
+
+template <class T, int NW, int NM, int GW, int NB>
+struct WaveLayout {
+  static constexpr int C = NW * NM;
+  static constexpr int SMX = GW + NW;  // member states + shadow states
+  static constexpr int NZ = 4;         // Z ring slots (q-lines in flight)
+  __host__ __device__ static size_t z_bytes() { return align16(sizeof(typename V2<T>::t) * NZ * GW * NB * C); }
+  __host__ __device__ static int qcap(int N) { return 64 + SMX * N; }
+  __host__ __device__ static size_t q_bytes(int N) { return align16(4 * (size_t)qcap(N)); }
+  __host__ __device__ static size_t misc_bytes() { return align16(SMX * 8 + SMX * 4 * 4 + NZ * 8 + 64); }
+  __host__ __device__ static size_t line_bytes(int N) { return align16(8 * (size_t)N * NW); }
+  __host__ __device__ static size_t per_wave(int N) { return z_bytes() + q_bytes(N) + misc_bytes() + line_bytes(N); }
+  __host__ __device__ static size_t tab_bytes(int N) { return align16(sizeof(typename V2<T>::t) * N); }
+  __host__ __device__ static size_t total(int N) { return tab_bytes(N) + 4 * per_wave(N); }
+};
+
+#ifndef EPH_WAVE_OCC
+#define EPH_WAVE_OCC 2
+#endif
+template <class T, int NW, int NM, int GW, int NB, int LPL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OCC))) void rates_wave_kernel(
+    RatesArgs a) {
+  using C2 = typename V2<T>::t;
+  using LY = WaveLayout<T, NW, NM, GW, NB>;
+  constexpr int C = NW * NM;
+  constexpr int SMX = LY::SMX;
+  constexpr int NZ = LY::NZ;
+  constexpr int NPAIR = (GW * NB * C + 63) / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = a.N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int LN = N * NW;
+
+  C2 *sTab = reinterpret_cast<C2 *>(smem);
+  unsigned char *wb = smem + LY::tab_bytes(N) + (size_t)wave * LY::per_wave(N);
+  C2 *sZ = reinterpret_cast<C2 *>(wb);  // [NZ][GW][NB][C]
+  uint32_t *sQ = reinterpret_cast<uint32_t *>(wb + LY::z_bytes());
+  unsigned char *misc = wb + LY::z_bytes() + LY::q_bytes(N);
+  double *sEps = reinterpret_cast<double *>(misc);  // [SMX] state energies
+  int *sKs = reinterpret_cast<int *>(sEps + SMX);     // [SMX] k-slot of each state
+  int *sKfirst = sKs + SMX;                           // [SMX] first state of each k-slot
+  int *sKcnt = sKfirst + SMX;                         // [SMX] states of each k-slot
+  int *sK1 = sKcnt + SMX;                             // [SMX] k1 of each k-slot
+  int *sSlot = sK1 + SMX;                             // [NZ][2] (q2, line) of each Z slot
+  double *sLine = reinterpret_cast<double *>(misc + LY::misc_bytes());  // [NW][N] current line energies
+
+  for (int t = threadIdx.x; t < N; t += 256) sTab[t] = mk<T>((T)a.tab[t].x, (T)a.tab[t].y);
+  __syncthreads();  // the only workgroup barrier
+
+  // XCD-aware block order: consecutive block indices go round-robin to the
+  // 8 XCDs, so give each XCD a contiguous range of groups.
+  const int64_t nblk = (a.ng + 3) / 4;
+  const int64_t per_xcd = (nblk + 7) / 8;
+  const int64_t blk = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int64_t g = blk * 4 + wave;
+  if (blk >= nblk || g >= a.ng) return;  // wave-uniform
+
+  const int64_t s0 = a.gstart[g];
+  const int S = (int)(a.gstart[g + 1] - s0);
+  const int64_t kfirst = a.sk[s0];
+  int SH = 0;
+  {
+    const int64_t klast = a.sk[s0 + S - 1];
+    while (SH < NW - 1 && s0 + S + SH < a.ns_total && a.sk[s0 + S + SH] == klast) SH++;
+  }
+  const int ST = S + SH;
+  const bool cont = (s0 > 0) && (a.sk[s0 - 1] == kfirst);  // first k point counted by an earlier group
+  const int k2 = (int)((kfirst / N) % N), k3 = (int)(kfirst / ((int64_t)N * N));
+  const double W = a.wmax + a.sw * a.eta;
+  const double cut = a.sw * a.eta;
+  const double inv_eta = 1.0 / a.eta;
+  const double dnorm = 1.0 / (1.7724538509055160273 * a.eta);
+  const int nt = a.nt;
+  const int lo1 = a.box.lo[0], lo2 = a.box.lo[1], lo3 = a.box.lo[2];
+
+  // states and k-slots (distinct k points, states of one k are contiguous)
+  int NK = 0;
+  if (lane == 0) {
+    int64_t prev = -1;
+    for (int s = 0; s < ST; s++) {
+      const int64_t k = a.sk[s0 + s];
+      if (k != prev) {
+        sKfirst[NK] = s;
+        sKcnt[NK] = 0;
+        sK1[NK] = (int)(k % N);
+        NK++;
+        prev = k;
+      }
+      sKs[s] = NK - 1;
+      sKcnt[NK - 1]++;
+      sEps[s] = a.eps[k * NW + a.sn[s0 + s]];
+    }
+  }
+  NK = __shfl(NK, 0, 64);
+  __syncwarp();
+
+  double acc[GW][EPH_MAX_TEMPS];
+  unsigned nq_s[GW], nt_s[GW];
+#pragma unroll
+  for (int s = 0; s < GW; s++) {
+    nq_s[s] = nt_s[s] = 0u;
+#pragma unroll
+    for (int t = 0; t < EPH_MAX_TEMPS; t++) acc[s][t] = 0.0;
+  }
+  unsigned long long my_nkq = 0, my_nv = 0;
+
+  // pair slots of this lane: P = lane + 64 j -> (s, p1, c) = (P / (NB C), (P / C) % NB, P % C)
+  T yr[NPAIR][NB], yi[NPAIR][NB];
+  const C2 *Xg = reinterpret_cast<const C2 *>(a.X);
+  const int64_t xrow = (int64_t)NB * NB * NB * C;
+
+  // final-state line energies: the next q-line's are loaded into registers
+  // while the current one (in LDS, [m][p1]) is scanned
+  double nxt[LPL];
+  {
+    const int l3 = (k3 + a.q3_lo >= N) ? k3 + a.q3_lo - N : k3 + a.q3_lo;
+    const double *l0 = a.eps + (size_t)(k2 + N * l3) * LN;
+    for (int e = lane; e < LN; e += 64) sLine[(e % NW) * N + e / NW] = l0[e];
+  }
+
+  // One candidate = (k-slot, p1, Z slot): every state of that k point against
+  // every final band m at p = k + q.  drain(n) evaluates the first n queued.
+  int qn = 0;
+  auto drain = [&](int count) {
+    for (int base = 0; base < count; base += 64) {
+      const int i = base + lane;
+      if (i >= count) continue;
+      const uint32_t it = sQ[i];
+      const int p1 = (int)(it & 1023u), ks = (int)((it >> 10) & 31u), zs_slot = (int)(it >> 15);
+      const int q2 = sSlot[2 * zs_slot], line = sSlot[2 * zs_slot + 1];
+      int q1 = p1 - sK1[ks];
+      q1 += (q1 < 0) ? N : 0;
+      const int q3 = a.q3_cur;
+      const int64_t qidx = q1 + (int64_t)N * (q2 + (int64_t)N * q3);
+      const int64_t pidx = p1 + (int64_t)N * line;
+      double om[NM];
+#pragma unroll
+      for (int nu = 0; nu < NM; nu++) om[nu] = a.om[qidx * NM + nu];
+      bool hit = false;
+      const int sf = sKfirst[ks], sc = sKcnt[ks];
+      for (int s = sf; s < sf + sc; s++) {
+        const double es = sEps[s];
+        bool hit_s = false;
+        int nterm = 0;
+        double contrib[EPH_MAX_TEMPS];
+#pragma unroll
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = 0.0;
+#pragma unroll 1
+        for (int m = 0; m < NW; m++) {
+          const double epm = a.eps[pidx * NW + m];
+          unsigned vp = 0, vm = 0;
+#pragma unroll
+          for (int nu = 0; nu < NM; nu++) {
+            const bool okw = om[nu] >= a.wcut;
+            vp |= (okw && fabs(es + om[nu] - epm) <= cut) ? (1u << nu) : 0u;
+            vm |= (okw && fabs(es - om[nu] - epm) <= cut) ? (1u << nu) : 0u;
+          }
+          if ((vp | vm) == 0u) continue;
+          hit_s = true;
+          if (s >= S) continue;  // shadow state: counted, not computed
+          my_nv++;
+          C2 vrow[NW];
+#pragma unroll
+          for (int i2 = 0; i2 < NW; i2++) {
+            if constexpr (sizeof(T) == 8) vrow[i2] = a.evec[(pidx * NW + m) * NW + i2];
+            else vrow[i2] = a.evec32[(pidx * NW + m) * NW + i2];
+          }
+          // W_mu = sum_p1' e^{i 2pi q1 p1'/N} sum_i conj(V_im(p)) Z_s(p1'; mu, i)
+          T wr[NM], wi[NM];
+#pragma unroll
+          for (int mu = 0; mu < NM; mu++) wr[mu] = wi[mu] = 0;
+          int i1 = imod(q1 * lo1, N);
+          const C2 *zs = sZ + ((size_t)zs_slot * GW + s) * NB * C;
+#pragma unroll 1
+          for (int pp = 0; pp < NB; pp++) {
+            const C2 ph = sTab[i1];
+            i1 += q1;
+            i1 -= (i1 >= N) ? N : 0;
+#pragma unroll
+            for (int mu = 0; mu < NM; mu++) {
+              T tr = 0, ti = 0;
+#pragma unroll
+              for (int i2 = 0; i2 < NW; i2++) {
+                const C2 z = zs[pp * C + mu * NW + i2];
+                cmac_conj<T>(tr, ti, vrow[i2].x, vrow[i2].y, z.x, z.y);
+              }
+              cmac<T>(wr[mu], wi[mu], ph.x, ph.y, tr, ti);
+            }
+          }
+          double fo[EPH_MAX_TEMPS];
+#pragma unroll
+          for (int t = 0; t < EPH_MAX_TEMPS; t++) fo[t] = (t < nt) ? a.occ_f[(pidx * NW + m) * nt + t] : 0.0;
+#pragma unroll
+          for (int nu = 0; nu < NM; nu++) {
+            const bool okp = (vp >> nu) & 1u, okm = (vm >> nu) & 1u;
+            if (!(okp || okm)) continue;
+            T gr = 0, gi = 0;
+#pragma unroll
+            for (int mu = 0; mu < NM; mu++) {
+              C2 u;
+              if constexpr (sizeof(T) == 8) u = a.uu[(qidx * NM + nu) * NM + mu];
+              else u = a.uu32[(qidx * NM + nu) * NM + mu];
+              cmac<T>(gr, gi, wr[mu], wi[mu], u.x, u.y);
+            }
+            const double g2 = fma((double)gr, (double)gr, (double)gi * (double)gi);
+            const double xp = es + om[nu] - epm, xm = es - om[nu] - epm;
+            const double dp = okp ? exp(-(xp * inv_eta) * (xp * inv_eta)) * dnorm : 0.0;
+            const double dm = okm ? exp(-(xm * inv_eta) * (xm * inv_eta)) * dnorm : 0.0;
+            nterm += (int)okp + (int)okm;
+#pragma unroll
+            for (int t = 0; t < EPH_MAX_TEMPS; t++) {
+              if (t < nt) {
+                const double nq = a.occ_n[(qidx * NM + nu) * nt + t];
+                contrib[t] = fma(g2, fma(nq + fo[t], dp, (1.0 + nq - fo[t]) * dm), contrib[t]);
+              }
+            }
+          }
+        }
+        hit = hit || hit_s;
+#pragma unroll
+        for (int ss = 0; ss < GW; ss++)
+          if (ss == s) {
+#pragma unroll
+            for (int t = 0; t < EPH_MAX_TEMPS; t++) acc[ss][t] += contrib[t];
+            nq_s[ss] += hit_s ? 1u : 0u;
+            nt_s[ss] += (unsigned)nterm;
+          }
+      }
+      if (hit && !(cont && ks == 0)) my_nkq++;
+    }
+  };
+  // drop the first n entries of the queue (after they were evaluated)
+  auto pop = [&](int n) {
+    const int rem = qn - n;
+    for (int b = 0; b < rem; b += 64) {
+      const uint32_t v = (b + lane < rem) ? sQ[n + b + lane] : 0u;
+      __syncwarp();
+      if (b + lane < rem) sQ[b + lane] = v;
+      __syncwarp();
+    }
+    qn = rem;
+  };
+
+  int ql = 0;  // q-lines started in this launch
+  for (int q3 = a.q3_lo; q3 < a.q3_hi; q3++) {
+    // ---- Y_s(p1, p2; q3) into registers (p3 loop rolled) ----
+#pragma unroll
+    for (int j = 0; j < NPAIR; j++)
+#pragma unroll
+      for (int p2 = 0; p2 < NB; p2++) yr[j][p2] = yi[j][p2] = 0;
+    {
+      int i3 = imod(q3 * lo3, N);
+#pragma unroll 1
+      for (int p3 = 0; p3 < NB; p3++) {
+        const C2 ph = sTab[i3];
+        i3 += q3;
+        i3 -= (i3 >= N) ? N : 0;
+#pragma unroll
+        for (int j = 0; j < NPAIR; j++) {
+          const int P = lane + 64 * j;
+          const int s = P / (NB * C), p1 = (P / C) % NB, c = P % C;
+          if (s < S) {
+            const C2 *xs = Xg + (s0 + s - a.s_base) * xrow + (int64_t)p1 * NB * NB * C + p3 * C + c;
+#pragma unroll
+            for (int p2 = 0; p2 < NB; p2++) {
+              const C2 x = xs[p2 * NB * C];
+              cmac<T>(yr[j][p2], yi[j][p2], ph.x, ph.y, x.x, x.y);
+            }
+          }
+        }
+      }
+    }
+    const int p3line = (k3 + q3 >= N) ? k3 + q3 - N : k3 + q3;
+    for (int q2 = 0; q2 < N; q2++, ql++) {
+      {  // issue the loads of the next q-line's energies
+        int nq2 = q2 + 1, nq3 = q3;
+        if (nq2 == N) {
+          nq2 = 0;
+          nq3 = (q3 + 1 == N) ? 0 : q3 + 1;
+        }
+        const int n2l = (k2 + nq2 >= N) ? k2 + nq2 - N : k2 + nq2;
+        const int n3l = (k3 + nq3 >= N) ? k3 + nq3 - N : k3 + nq3;
+        const double *ln = a.eps + (size_t)(n2l + N * n3l) * LN;
+#pragma unroll
+        for (int i = 0; i < LPL; i++) {
+          const int e = lane + 64 * i;
+          nxt[i] = (e < LN) ? ln[e] : 0.0;
+        }
+      }
+      const int zslot = ql & (NZ - 1);
+      {  // the Z slot is reused: evaluate queued candidates that still point at it
+        bool stale = false;
+        for (int b = 0; b < qn; b += 64)
+          stale |= (b + lane < qn) && (int)(sQ[b + lane] >> 15) == zslot;
+        if (__any(stale)) {
+          drain(qn);
+          __syncwarp();
+          qn = 0;
+        }
+      }
+      // ---- Z_s(p1; q2, q3) -> LDS slot ----
+      C2 ph2[NB];
+      {
+        int i2 = imod(q2 * lo2, N);
+#pragma unroll
+        for (int p = 0; p < NB; p++) {
+          ph2[p] = sTab[i2];
+          i2 += q2;
+          i2 -= (i2 >= N) ? N : 0;
+        }
+      }
+      C2 *zslot_base = sZ + (size_t)zslot * GW * NB * C;
+#pragma unroll
+      for (int j = 0; j < NPAIR; j++) {
+        const int P = lane + 64 * j;
+        if (P < GW * NB * C) {
+          T r = 0, i = 0;
+#pragma unroll
+          for (int p2 = 0; p2 < NB; p2++) cmac<T>(r, i, ph2[p2].x, ph2[p2].y, yr[j][p2], yi[j][p2]);
+          zslot_base[P] = mk<T>(r, i);
+        }
+      }
+      const int p2line = (k2 + q2 >= N) ? k2 + q2 - N : k2 + q2;
+      const int line = p2line + N * p3line;
+      if (lane == 0) {
+        sSlot[2 * zslot] = q2;
+        sSlot[2 * zslot + 1] = line;
+      }
+      __syncwarp();
+      // ---- candidates of this q-line: (k-slot, p1) with some band in the window ----
+      for (int ks = 0; ks < NK; ks++) {
+        const int sf = sKfirst[ks], sc = sKcnt[ks];
+        for (int c0 = 0; c0 < N; c0 += 64) {
+          const int p1 = c0 + lane;
+          bool any = false;
+          if (p1 < N) {
+#pragma unroll
+            for (int m = 0; m < NW; m++) {
+              const double ev = sLine[m * N + p1];
+              for (int s = sf; s < sf + sc; s++) any |= fabs(ev - sEps[s]) <= W;
+            }
+          }
+          const unsigned long long bits = __ballot(any);
+          if (any) sQ[qn + __popcll(bits & ((1ull << lane) - 1ull))] =
+              (uint32_t)p1 | ((uint32_t)ks << 10) | ((uint32_t)zslot << 15);
+          qn += __popcll(bits);
+        }
+      }
+      __syncwarp();
+      if (qn >= 64) {  // evaluate whole passes only; the rest waits for later q-lines
+        const int full = qn & ~63;
+        drain(full);
+        __syncwarp();
+        pop(full);
+      }
+      // stage the next line's energies ([m][p1] in LDS)
+#pragma unroll
+      for (int i = 0; i < LPL; i++) {
+        const int e = lane + 64 * i;
+        if (e < LN) sLine[(e % NW) * N + e / NW] = nxt[i];
+      }
+      __syncwarp();
+    }
+  }
+  drain(qn);
+
+  // ---- fixed-order reductions; q3 slabs add up in launch order ----
+#pragma unroll
+  for (int s = 0; s < GW; s++) {
+#pragma unroll
+    for (int t = 0; t < EPH_MAX_TEMPS; t++) {
+      double v = acc[s][t];
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+      if (lane == 0 && s < S && t < nt) {
+        double *dst = a.inv_tau + (int64_t)t * a.ns_total + s0 + s;
+        *dst = (a.q3_lo == 0 ? 0.0 : *dst) + a.pref * v;
+      }
+    }
+    unsigned long long c1 = nq_s[s], c2 = nt_s[s];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      c1 += __shfl_xor(c1, m, 64);
+      c2 += __shfl_xor(c2, m, 64);
+    }
+    if (lane == 0 && s < S) {
+      int64_t *dst = a.st_counts + (s0 + s) * 2;
+      dst[0] = (a.q3_lo == 0 ? 0 : dst[0]) + (int64_t)c1;
+      dst[1] = (a.q3_lo == 0 ? 0 : dst[1]) + (int64_t)c2;
+    }
+  }
+  unsigned long long v1 = my_nkq, v2 = my_nv;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    v1 += __shfl_xor(v1, m, 64);
+    v2 += __shfl_xor(v2, m, 64);
+  }
+  if (lane == 0) {
+    atomicAdd(a.n_kq, v1);
+    atomicAdd(a.n_vertex, v2);
+  }
+}
+
+template <class T, int NW, int NM, int GW, int NB, int LPL>
+hipError_t launch_wave_l(const RatesArgs &a, hipStream_t st) {
+  using LY = WaveLayout<T, NW, NM, GW, NB>;
+  const size_t sh = LY::total(a.N);
+  if (sh > 160 * 1024) return hipErrorInvalidValue;
+  auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  const int64_t nblk = (a.ng + 3) / 4;
+  const int64_t grid = ((nblk + 7) / 8) * 8;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), sh, st, a);
+  return hipGetLastError();
+}
+
+template <class T, int NW, int NM, int GW, int NB>
+hipError_t launch_wave(const RatesArgs &a, hipStream_t st) {
+  const int ln = a.N * NW;
+  if (ln <= 512) return launch_wave_l<T, NW, NM, GW, NB, 8>(a, st);
+  if (ln <= 1024) return launch_wave_l<T, NW, NM, GW, NB, 16>(a, st);
+  if (ln <= 2048) return launch_wave_l<T, NW, NM, GW, NB, 32>(a, st);
+  return hipErrorNotSupported;
+}
+
+}  // namespace
+
+// Shapes served by the wave-autonomous kernel (cubic Rp box of edge 4 or 6).
+int rates_wave_group(int nw, int nm, RpBox box, int N) {
+  const bool cube = box.n[0] == box.n[1] && box.n[1] == box.n[2] && (box.n[0] == 4 || box.n[0] == 6);
+  if (!cube || N * nw > 2048) return 0;
+  if (nm == 3 && (nw == 1 || nw == 2 || nw == 4)) return 2;
+  if (nm == 3 && nw == 8) return 1;
+  if (nm == 6 && (nw == 1 || nw == 2)) return 2;
+  if (nm == 6 && (nw == 4 || nw == 8)) return 1;
+  return 0;
+}
+
+template <class T>
+static hipError_t wave_dispatch(const RatesArgs &a, hipStream_t st) {
+  const int nb = a.box.n[0];
+#define EPH_W(NW_, NM_, GW_)                                         \
+  if (a.nw == NW_ && a.nm == NM_) {                                  \
+    if (nb == 4) return launch_wave<T, NW_, NM_, GW_, 4>(a, st);     \
+    if (nb == 6) return launch_wave<T, NW_, NM_, GW_, 6>(a, st);     \
+  }
+  EPH_W(1, 3, 2)
+  EPH_W(2, 3, 2)
+  EPH_W(4, 3, 2)
+  EPH_W(8, 3, 1)
+  EPH_W(1, 6, 2)
+  EPH_W(2, 6, 2)
+  EPH_W(4, 6, 1)
+  EPH_W(8, 6, 1)
+#undef EPH_W
+  return hipErrorNotSupported;
+}
+
+hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st) {
+  if (a.ng <= 0) return hipSuccess;
+  if (precision == EPH_FP64) return wave_dispatch<double>(a, st);
+  return wave_dispatch<float>(a, st);
+}
+
+}  // namespace eph

@@ -53,7 +53,35 @@ __global__ void summarize_kernel(int64_t ns, const int64_t *__restrict__ st_coun
   if (threadIdx.x < 3) atomicAdd(out + threadIdx.x, red[threadIdx.x][0]);
 }
 
+struct Kts {
+  double v[EPH_MAX_TEMPS];
+};
+
+__global__ void occupation_kernel(int64_t nq, int nw, int nm, const double *__restrict__ eps,
+                                  const double *__restrict__ om, double mu, int nt, Kts kts, double wcut,
+                                  double *__restrict__ occ_f, double *__restrict__ occ_n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nq * nw) {
+    const double e = eps[i];
+    for (int t = 0; t < nt; t++) occ_f[i * nt + t] = 1.0 / (exp((e - mu) / kts.v[t]) + 1.0);
+  }
+  if (i < nq * nm) {
+    const double w = om[i];
+    for (int t = 0; t < nt; t++) occ_n[i * nt + t] = (w >= wcut && w > 0.0) ? 1.0 / expm1(w / kts.v[t]) : 0.0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_occupations(int64_t nq, int nw, int nm, const double *eps, const double *om, double mu, int nt,
+                              const double *kts_host, double wcut, double *occ_f, double *occ_n, hipStream_t st) {
+  Kts k;
+  for (int t = 0; t < EPH_MAX_TEMPS; t++) k.v[t] = t < nt ? kts_host[t] : 1.0;
+  const int64_t n = nq * (nw > nm ? nw : nm);
+  hipLaunchKernelGGL(occupation_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nq, nw, nm, eps, om,
+                     mu, nt, k, wcut, occ_f, occ_n);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
   int64_t n64 = (int64_t)((bytes + 7) / 8);

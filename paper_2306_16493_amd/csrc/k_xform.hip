@@ -5,6 +5,7 @@
 // X[s][col] = sum_kk B[s][kk] W[kk][col] with kk = (Re, j) and
 // col = (Rp, mu, i); the state-side operand B (a phase times one
 // eigenvector component) is generated on the fly into LDS.
+#include "dev_util.h"
 #include "internal.h"
 
 namespace eph {
@@ -16,24 +17,28 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-__global__ __launch_bounds__(256) void xform64_kernel(int64_t ns, const int32_t *__restrict__ sk,
-                                                      const int32_t *__restrict__ sn, int N, int nw, int nre,
-                                                      const int *__restrict__ re, int ncol,
-                                                      const double2 *__restrict__ wt,
-                                                      const double2 *__restrict__ evec,
-                                                      const double2 *__restrict__ tab, double2 *__restrict__ X) {
-  __shared__ double2 sB[BM][BK + 1];
-  __shared__ double2 sW[BK][BN];
+// T = accumulation/operand type (double for the FP64 form, float for FP32).
+template <class T>
+__global__ __launch_bounds__(256) void xform_kernel(int64_t ns, const int32_t *__restrict__ sk,
+                                                    const int32_t *__restrict__ sn, int N, int nw, int nre,
+                                                    const int *__restrict__ re, int ncol,
+                                                    const typename V2<T>::t *__restrict__ wt,
+                                                    const double2 *__restrict__ evec,
+                                                    const double2 *__restrict__ tab,
+                                                    typename V2<T>::t *__restrict__ X) {
+  using C2 = typename V2<T>::t;
+  __shared__ C2 sB[BM][BK + 1];
+  __shared__ C2 sW[BK][BN];
   const int tid = threadIdx.x;
   const int tx = tid % 16, ty = tid / 16;
   const int64_t s0 = (int64_t)blockIdx.y * BM;
   const int c0 = blockIdx.x * BN;
   const int K = nre * nw;
-  double2 acc[4][4];
+  C2 acc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; r++)
 #pragma unroll
-    for (int c = 0; c < 4; c++) acc[r][c] = make_double2(0.0, 0.0);
+    for (int c = 0; c < 4; c++) acc[r][c] = mk<T>(0, 0);
 
   for (int kk0 = 0; kk0 < K; kk0 += BK) {
     // state-side operand: phase(k_s, Re) * V_{j n_s}(k_s)
@@ -41,7 +46,7 @@ __global__ __launch_bounds__(256) void xform64_kernel(int64_t ns, const int32_t 
       int sl = t / BK, kl = t % BK;
       int64_t s = s0 + sl;
       int kk = kk0 + kl;
-      double2 v = make_double2(0.0, 0.0);
+      double2 v = make_double2(0.0, 0.0);  // phase and eigenvector product in FP64, then T
       if (s < ns && kk < K) {
         int64_t k = sk[s];
         int n = sn[s];
@@ -51,17 +56,17 @@ __global__ __launch_bounds__(256) void xform64_kernel(int64_t ns, const int32_t 
         if (ph < 0) ph += N;
         v = cmul(tab[ph], evec[(k * nw + n) * nw + j]);
       }
-      sB[sl][kl] = v;
+      sB[sl][kl] = mk<T>((T)v.x, (T)v.y);
     }
     for (int t = tid; t < BK * BN; t += 256) {
       int kl = t / BN, cl = t % BN;
       int kk = kk0 + kl, c = c0 + cl;
-      sW[kl][cl] = (kk < K && c < ncol) ? wt[(size_t)kk * ncol + c] : make_double2(0.0, 0.0);
+      sW[kl][cl] = (kk < K && c < ncol) ? wt[(size_t)kk * ncol + c] : mk<T>(0, 0);
     }
     __syncthreads();
 #pragma unroll 4
     for (int kl = 0; kl < BK; kl++) {
-      double2 a[4], b[4];
+      C2 a[4], b[4];
 #pragma unroll
       for (int r = 0; r < 4; r++) a[r] = sB[ty * 4 + r][kl];
 #pragma unroll
@@ -97,7 +102,18 @@ hipError_t launch_xform64(int64_t ns, const int32_t *sk, const int32_t *sn, int 
                           hipStream_t st) {
   if (ns <= 0) return hipSuccess;
   dim3 grid((ncol + BN - 1) / BN, (unsigned)((ns + BM - 1) / BM));
-  hipLaunchKernelGGL(xform64_kernel, grid, dim3(256), 0, st, ns, sk, sn, N, nw, nre, re, ncol, wt, evec, tab, X);
+  hipLaunchKernelGGL(xform_kernel<double>, grid, dim3(256), 0, st, ns, sk, sn, N, nw, nre, re, ncol, wt, evec,
+                     tab, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_xform32(int64_t ns, const int32_t *sk, const int32_t *sn, int N, int nw, int nre, const int *re,
+                          int ncol, const float2 *wt, const double2 *evec, const double2 *tab, float2 *X,
+                          hipStream_t st) {
+  if (ns <= 0) return hipSuccess;
+  dim3 grid((ncol + BN - 1) / BN, (unsigned)((ns + BM - 1) / BM));
+  hipLaunchKernelGGL(xform_kernel<float>, grid, dim3(256), 0, st, ns, sk, sn, N, nw, nre, re, ncol, wt, evec,
+                     tab, X);
   return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libeph.so")
+LIB_PATH = os.environ.get("EPH_LIB", os.path.join(_HERE, "libeph.so"))
 
 EPH_OK, EPH_E_INVALID, EPH_E_NOMEM, EPH_E_DEVICE, EPH_E_STATE, EPH_E_TRUNCATED, EPH_E_UNSUPPORTED = range(7)
 EPH_FP64, EPH_FP32, EPH_BF16X3 = 0, 1, 2
