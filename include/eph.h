@@ -173,6 +173,13 @@ int32_t eph_scattering_rates(eph_ctx *ctx, const eph_rates_params *params, int64
                              int32_t *state_k, int32_t *state_n, double *energy_eV,
                              double *vel_ms, double *inv_tau_s, eph_counts *counts);
 
+/* The state selection of eph_scattering_rates alone: the same grid tables
+ * and window, the same outputs except inv_tau, no rates (all counts other
+ * than n_states and n_excluded_modes are 0).  Used by callers that compute
+ * rates for a part of the states only (k_subset) or estimate them. */
+int32_t eph_select_states(eph_ctx *ctx, const eph_rates_params *params, int64_t capacity, int32_t *state_k,
+                          int32_t *state_n, double *energy_eV, double *vel_ms, eph_counts *counts);
+
 /* Conductivity tensor (Sec. II.C) from per-state data, in S/m:
  *   sigma_ab(T) = 2 e^2/(n_kpoints V) sum_s v_a v_b tau_s f(1-f)/(k_B T),
  * tau_s = 1/inv_tau_s(T); states with inv_tau = 0 are skipped.  V is the
@@ -201,6 +208,70 @@ int32_t eph_conductivity(eph_ctx *ctx, int64_t n_states, const double *energy_eV
  * synchronisation beyond the one each call already does. */
 int32_t eph_set_profiling(eph_ctx *ctx, int32_t on);
 int32_t eph_stage_times(const eph_ctx *ctx, double *ms, int64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Learned form: an ensemble of multilayer perceptrons that predicts
+ * log(1/tau) of a state from its features, trained on rates that
+ * eph_scattering_rates computed on a subset of k points.  Where the members
+ * disagree the caller recomputes the rates with eph_scattering_rates
+ * (k_subset) and merges them with eph_merge_rates.  This form is not in the
+ * paper; it stands beside the SERTA rates of Sec. II.C.
+ * Network: features (7) -> 128 -> 128 -> 128 -> n_out, SiLU, FP32; Adam on
+ * the mean squared error of normalised log(1/tau); n_out = temperatures.
+ * Parameter layout per member (row-major W[out][in]):
+ *   W1[128][7] b1[128] W2[128][128] b2 W3[128][128] b3 W4[n_out][128] b4.
+ * All array arguments are DEVICE pointers unless marked host.
+ * ------------------------------------------------------------------------ */
+typedef struct eph_mlp eph_mlp;
+
+/* Create n_members (1..64) networks with n_out (1..EPH_MAX_TEMPS) outputs,
+ * weights drawn from a counter-based hash of seed.  Errors: EPH_E_INVALID,
+ * EPH_E_NOMEM, EPH_E_DEVICE. */
+int32_t eph_mlp_create(eph_ctx *ctx, int32_t n_members, int32_t n_out, uint64_t seed, eph_mlp **out);
+void eph_mlp_free(eph_mlp *mlp); /* NULL-safe */
+
+/* Parameter count per member in *n_params; with host_params non-NULL, copy
+ * all members' parameters ([n_members][n_params] floats) out (set = 0) or
+ * in (set = 1). */
+int32_t eph_mlp_params(eph_mlp *mlp, float *host_params, int64_t *n_params, int32_t set);
+
+/* Features x[n][7] = (k1/N, k2/N, k3/N, eps - mu [eV], v [1e6 m/s] x3) of
+ * states (state_k, energy_eV, vel_ms as returned by eph_scattering_rates);
+ * with inv_tau_s ([n_temps][n]) also the targets y[n][n_temps] =
+ * log(inv_tau).  Enqueued on stream. */
+int32_t eph_mlp_features(eph_ctx *ctx, int64_t n, const int32_t *state_k, const double *energy_eV,
+                         const double *vel_ms, int32_t grid, double mu_eV, const double *inv_tau_s,
+                         int32_t n_temps, float *x, float *y, void *stream);
+
+/* Train every member for `steps` Adam steps (lr, beta 0.9/0.999) on
+ * minibatches of `batch` samples (multiple of 32) drawn independently per
+ * member from the n samples.  The first call fixes the input/target
+ * normalisation from its data.  loss (host, may be NULL) receives each
+ * member's last minibatch loss.  Synchronises the stream. */
+int32_t eph_mlp_train(eph_mlp *mlp, int64_t n, const float *x, const float *y, int32_t steps,
+                      int32_t batch, float lr, void *stream, float *loss);
+
+/* Gradient of the loss over all n samples (multiple of 32, taken as already
+ * normalised) w.r.t. every parameter, into grad (host, [n_members][n_params]);
+ * loss (host, may be NULL) per member.  For checking the backward kernels. */
+int32_t eph_mlp_gradient(eph_mlp *mlp, int64_t n, const float *x, const float *y, float *grad, float *loss);
+
+/* y[n_members][n][n_out] = each member's prediction of log(1/tau). */
+int32_t eph_mlp_predict(eph_mlp *mlp, int64_t n, const float *x, float *y, void *stream);
+
+/* Ensemble mean of exp(y) into inv_tau_s [n_out][n]; flag[s] = 1 where the
+ * relative spread (std / mean over members, largest over outputs) exceeds
+ * threshold; *n_flagged (host) counts them.  Synchronises the stream. */
+int32_t eph_mlp_blend(eph_mlp *mlp, int64_t n, const float *y, double threshold, double *inv_tau_s,
+                      int32_t *flag, int64_t *n_flagged, void *stream);
+
+/* Overwrite full_inv_tau [n_temps][n_full] at the states (k, n) of the sub
+ * list with sub_inv_tau [n_temps][n_sub]; both lists sorted by k then n, as
+ * eph_scattering_rates returns them.  Sub states absent from the full list
+ * are ignored. */
+int32_t eph_merge_rates(eph_ctx *ctx, int64_t n_full, const int32_t *full_k, const int32_t *full_n,
+                        int64_t n_sub, const int32_t *sub_k, const int32_t *sub_n, const double *sub_inv_tau,
+                        int32_t n_temps, double *full_inv_tau, void *stream);
 
 #ifdef __cplusplus
 }

@@ -273,9 +273,9 @@ int32_t eph_load_wannier(const eph_model *m, int32_t device, eph_ctx **out) {
   return EPH_OK;
 }
 
-int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
-                             int32_t *state_n, double *energy_eV, double *vel_ms, double *inv_tau_s,
-                             eph_counts *counts) {
+static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
+                          int32_t *state_n, double *energy_eV, double *vel_ms, double *inv_tau_s,
+                          eph_counts *counts, bool states_only) {
   if (!c) return EPH_E_INVALID;
   c->err.clear();
   if (!p) return fail(c, EPH_E_INVALID, "params is NULL");
@@ -293,11 +293,10 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
     return fail(c, EPH_E_INVALID, "mu / window must be numbers");
   if (p->precision != EPH_FP64 && p->precision != EPH_FP32 && p->precision != EPH_BF16X3)
     return fail(c, EPH_E_INVALID, "unknown precision");
-  if (p->precision == EPH_BF16X3) return fail(c, EPH_E_UNSUPPORTED, "BF16x3 form not built");
   const int blo = p->band_lo, bhi = p->band_hi < 0 ? c->nw - 1 : p->band_hi;
   if (blo < 0 || blo > bhi || bhi >= c->nw) return fail(c, EPH_E_INVALID, "band range outside 0..n_wann-1");
   if (capacity < 0) return fail(c, EPH_E_INVALID, "capacity < 0");
-  if (capacity > 0 && (!state_k || !state_n || !energy_eV || !vel_ms || !inv_tau_s))
+  if (capacity > 0 && (!state_k || !state_n || !energy_eV || !vel_ms || (!inv_tau_s && !states_only)))
     return fail(c, EPH_E_INVALID, "NULL output buffer");
   const int64_t NQ = (int64_t)N * N * N;
   std::vector<int64_t> klist;
@@ -347,9 +346,14 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
     EPH_HIP(c, launch_to_f32(NQ * nw * nw, c->evec.as<double2>(), c->evec32.as<float2>(), st));
     EPH_HIP(c, launch_to_f32(NQ * nm * nm, c->uu.as<double2>(), c->uu32.as<float2>(), st));
     const size_t nwt = (size_t)c->nre * nw * c->box.count() * nm * nw;
-    if (c->wt32.bytes < sizeof(float2) * nwt) {
+    if (p->precision == EPH_FP32 && c->wt32.bytes < sizeof(float2) * nwt) {
       EPH_HIP(c, c->wt32.ensure(sizeof(float2) * nwt));
       EPH_HIP(c, launch_to_f32((int64_t)nwt, c->wt64.as<double2>(), c->wt32.as<float2>(), st));
+    }
+    const size_t nbf = 2 * bf16_w_elems(c->nre, nw, c->box.count() * nm * nw) * 2;  // hi + lo, 2 bytes each
+    if (p->precision == EPH_BF16X3 && c->wtbf.bytes < nbf) {
+      EPH_HIP(c, c->wtbf.ensure(nbf));
+      EPH_HIP(c, launch_split_bf16(c->nre, nw, c->box.count() * nm * nw, c->wt64.as<double2>(), c->wtbf.p, st));
     }
   }
   EPH_HIP(c, tm.mark(&e_tables));
@@ -381,6 +385,11 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
   }
   EPH_HIP(c, launch_write_states(nkl, d_klist, nw, c->eps.as<double>(), c->vel.as<double>(), blo, bhi, p->win_lo_eV,
                                  p->win_hi_eV, c->offs.as<int64_t>(), state_k, state_n, energy_eV, vel_ms, st));
+  if (states_only) {
+    EPH_HIP(c, hipStreamSynchronize(st));
+    if (counts) *counts = cn;
+    return EPH_OK;
+  }
 
   if (ns > 0) {
     // ---- groups of states sharing a k-line ----
@@ -485,7 +494,11 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
       EPH_HIP(c, c->xbuf.ensure(xrow * (size_t)(sb - sa)));
       int eb0, eb1, eb2;
       EPH_HIP(c, tm.mark(&eb0));
-      if (fp32)
+      if (p->precision == EPH_BF16X3)
+        EPH_HIP(c, launch_xform_bf16x3(sb - sa, state_k + sa, state_n + sa, N, nw, c->nre, c->re.as<int>(), ncol,
+                                       c->wtbf.p, c->evec.as<double2>(), c->tab.as<double2>(),
+                                       c->xbuf.as<float2>(), st));
+      else if (fp32)
         EPH_HIP(c, launch_xform32(sb - sa, state_k + sa, state_n + sa, N, nw, c->nre, c->re.as<int>(), ncol,
                                   c->wt32.as<float2>(), c->evec.as<double2>(), c->tab.as<double2>(),
                                   c->xbuf.as<float2>(), st));
@@ -541,6 +554,17 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
   cn.n_vertex = (int64_t)hc[6];
   if (counts) *counts = cn;
   return EPH_OK;
+}
+
+int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
+                             int32_t *state_n, double *energy_eV, double *vel_ms, double *inv_tau_s,
+                             eph_counts *counts) {
+  return rates_impl(c, p, capacity, state_k, state_n, energy_eV, vel_ms, inv_tau_s, counts, false);
+}
+
+int32_t eph_select_states(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
+                          int32_t *state_n, double *energy_eV, double *vel_ms, eph_counts *counts) {
+  return rates_impl(c, p, capacity, state_k, state_n, energy_eV, vel_ms, nullptr, counts, true);
 }
 
 int32_t eph_set_profiling(eph_ctx *c, int32_t on) {

@@ -129,6 +129,12 @@ hipError_t launch_xform32(int64_t ns, const int32_t *sk, const int32_t *sn, int 
                           const int *re, int ncol, const float2 *wt, const double2 *evec,
                           const double2 *tab, float2 *X, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double2 *in, float2 *out, hipStream_t st);
+// bf16 hi/lo split of the g operand in real form (2 * bf16_w_elems bf16 values)
+size_t bf16_w_elems(int nre, int nw, int ncol);
+hipError_t launch_split_bf16(int nre, int nw, int ncol, const double2 *wt, void *out, hipStream_t st);
+hipError_t launch_xform_bf16x3(int64_t ns, const int32_t *sk, const int32_t *sn, int N, int nw, int nre,
+                               const int *re, int ncol, const void *wbf, const double2 *evec,
+                               const double2 *tab, float2 *X, hipStream_t st);
 
 struct RatesArgs {
   int N, nw, nm, nt;

@@ -23,8 +23,11 @@ PRECISIONS = {"fp64": EPH_FP64, "fp32": EPH_FP32, "bf16x3": EPH_BF16X3}
 MAX_TEMPS = 4
 
 # every symbol declared in include/eph.h
-EXPORTS = ("eph_load_wannier", "eph_free", "eph_last_error", "eph_scattering_rates", "eph_conductivity",
-           "eph_set_profiling", "eph_stage_times")
+EXPORTS = ("eph_load_wannier", "eph_free", "eph_last_error", "eph_scattering_rates", "eph_select_states",
+           "eph_conductivity",
+           "eph_set_profiling", "eph_stage_times", "eph_mlp_create", "eph_mlp_free", "eph_mlp_params",
+           "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient", "eph_mlp_predict", "eph_mlp_blend",
+           "eph_merge_rates")
 
 
 class EphError(RuntimeError):
@@ -77,6 +80,9 @@ def lib():
         L.eph_scattering_rates.argtypes = [C.c_void_p, C.POINTER(RatesParams), C.c_int64, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Counts)]
         L.eph_scattering_rates.restype = C.c_int32
+        L.eph_select_states.argtypes = [C.c_void_p, C.POINTER(RatesParams), C.c_int64, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.POINTER(Counts)]
+        L.eph_select_states.restype = C.c_int32
         L.eph_conductivity.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                        C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.eph_conductivity.restype = C.c_int32
@@ -84,6 +90,20 @@ def lib():
         L.eph_set_profiling.restype = C.c_int32
         L.eph_stage_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.eph_stage_times.restype = C.c_int32
+        vp, i32, i64, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+        L.eph_mlp_create.argtypes = [vp, i32, i32, C.c_uint64, C.POINTER(vp)]
+        L.eph_mlp_free.argtypes = [vp]
+        L.eph_mlp_free.restype = None
+        L.eph_mlp_params.argtypes = [vp, vp, C.POINTER(i64), i32]
+        L.eph_mlp_features.argtypes = [vp, i64, vp, vp, vp, i32, f64, vp, i32, vp, vp, vp]
+        L.eph_mlp_train.argtypes = [vp, i64, vp, vp, i32, i32, f32, vp, vp]
+        L.eph_mlp_gradient.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.eph_mlp_predict.argtypes = [vp, i64, vp, vp, vp]
+        L.eph_mlp_blend.argtypes = [vp, i64, vp, f64, vp, vp, C.POINTER(i64), vp]
+        L.eph_merge_rates.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, i32, vp, vp]
+        for f in ("eph_mlp_create", "eph_mlp_params", "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient",
+                  "eph_mlp_predict", "eph_mlp_blend", "eph_merge_rates"):
+            getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
 
@@ -224,6 +244,21 @@ class Context:
         return dict(tables_ms=ms[0], prep_ms=ms[1], xform_ms=ms[2], rates_ms=ms[3], call_ms=ms[4],
                     xform_launches=int(ln[0]), rates_launches=int(ln[1]))
 
+    def select_states(self, params):
+        """(state_k, state_n, energy, vel) device tensors of the window states."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        ns = self.count_states(params)
+        cap = max(ns, 1)
+        k = torch.empty(cap, dtype=torch.int32, device=dev)
+        n = torch.empty(cap, dtype=torch.int32, device=dev)
+        e = torch.empty(cap, dtype=torch.float64, device=dev)
+        v = torch.empty(cap, 3, dtype=torch.float64, device=dev)
+        cnt = Counts()
+        self._check(lib().eph_select_states(self._h, C.byref(params), ns, _dptr(k), _dptr(n), _dptr(e), _dptr(v),
+                                            C.byref(cnt)))
+        return k[:ns], n[:ns], e[:ns], v[:ns]
+
     def conductivity(self, energy, vel, inv_tau, mu, temps, n_kpoints, stream=None):
         temps = np.ascontiguousarray(np.atleast_1d(temps), np.float64)
         out = np.zeros((temps.shape[0], 3, 3))
@@ -233,3 +268,88 @@ class Context:
                                     int(n_kpoints), C.c_void_p(stream) if stream else None, _ptr(out))
         self._check(st)
         return out
+
+
+class Mlp:
+    """An eph_mlp ensemble bound to a Context (device buffers are torch tensors)."""
+
+    def __init__(self, ctx: Context, members: int = 5, n_out: int = 1, seed: int = 0):
+        h = C.c_void_p()
+        st = lib().eph_mlp_create(ctx._h, int(members), int(n_out), C.c_uint64(seed), C.byref(h))
+        ctx._check(st)
+        self._h, self.ctx, self.members, self.n_out = h, ctx, int(members), int(n_out)
+        n = C.c_int64()
+        ctx._check(lib().eph_mlp_params(h, None, C.byref(n), 0))
+        self.n_params = int(n.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().eph_mlp_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def get_params(self):
+        out = np.zeros((self.members, self.n_params), np.float32)
+        self.ctx._check(lib().eph_mlp_params(self._h, _ptr(out), None, 0))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self.ctx._check(lib().eph_mlp_params(self._h, _ptr(p), None, 1))
+
+    def features(self, state_k, energy, vel, grid, mu, inv_tau=None, stream=None):
+        import torch
+        n = int(state_k.shape[0])
+        dev = state_k.device
+        x = torch.empty((max(n, 1), 7), dtype=torch.float32, device=dev)
+        y = None
+        nt = 0
+        if inv_tau is not None:
+            nt = int(inv_tau.shape[0])
+            y = torch.empty((max(n, 1), nt), dtype=torch.float32, device=dev)
+        st = lib().eph_mlp_features(self.ctx._h, n, _dptr(state_k), _dptr(energy.contiguous()),
+                                    _dptr(vel.contiguous()), int(grid), float(mu),
+                                    _dptr(inv_tau.contiguous()) if inv_tau is not None else None, nt,
+                                    _dptr(x), _dptr(y), C.c_void_p(stream) if stream else None)
+        self.ctx._check(st)
+        return x[:n], (y[:n] if y is not None else None)
+
+    def train(self, x, y, steps, batch=256, lr=1e-3, stream=None):
+        loss = np.zeros(self.members, np.float32)
+        st = lib().eph_mlp_train(self._h, int(x.shape[0]), _dptr(x), _dptr(y), int(steps), int(batch),
+                                 float(lr), C.c_void_p(stream) if stream else None, _ptr(loss))
+        self.ctx._check(st)
+        return loss
+
+    def gradient(self, x, y):
+        g = np.zeros((self.members, self.n_params), np.float32)
+        loss = np.zeros(self.members, np.float32)
+        self.ctx._check(lib().eph_mlp_gradient(self._h, int(x.shape[0]), _dptr(x), _dptr(y), _ptr(g), _ptr(loss)))
+        return loss, g
+
+    def predict(self, x, stream=None):
+        import torch
+        n = int(x.shape[0])
+        y = torch.empty((self.members, max(n, 1), self.n_out), dtype=torch.float32, device=x.device)
+        self.ctx._check(lib().eph_mlp_predict(self._h, n, _dptr(x), _dptr(y), C.c_void_p(stream) if stream else None))
+        return y[:, :n]
+
+    def blend(self, y, threshold, stream=None):
+        import torch
+        n = int(y.shape[1])
+        it = torch.empty((self.n_out, max(n, 1)), dtype=torch.float64, device=y.device)
+        flag = torch.empty(max(n, 1), dtype=torch.int32, device=y.device)
+        nf = C.c_int64()
+        self.ctx._check(lib().eph_mlp_blend(self._h, n, _dptr(y.contiguous()), float(threshold), _dptr(it),
+                                            _dptr(flag), C.byref(nf), C.c_void_p(stream) if stream else None))
+        return it[:, :n], flag[:n], int(nf.value)
+
+
+def merge_rates(ctx: Context, full_k, full_n, full_inv_tau, sub_k, sub_n, sub_inv_tau, stream=None):
+    """full_inv_tau[:, i] <- sub_inv_tau[:, j] where the (k, n) match (in place)."""
+    nt = int(full_inv_tau.shape[0])
+    st = lib().eph_merge_rates(ctx._h, int(full_k.shape[0]), _dptr(full_k), _dptr(full_n), int(sub_k.shape[0]),
+                               _dptr(sub_k), _dptr(sub_n), _dptr(sub_inv_tau.contiguous()), nt,
+                               _dptr(full_inv_tau), C.c_void_p(stream) if stream else None)
+    ctx._check(st)

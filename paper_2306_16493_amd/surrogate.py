@@ -1,0 +1,101 @@
+"""Surrogate-with-fallback driver of the scattering rates (argument
+marshalling and scheduling only; the arithmetic is in the HIP kernels).
+
+Steps, each a C-ABI call:
+  1. eph_select_states             every window state (k, n, eps, v);
+  2. eph_scattering_rates          plain rates on a seeded fraction of the
+                                   k points that carry states (training set);
+  3. eph_mlp_features/_train       an ensemble of MLPs fit to log(1/tau);
+  4. eph_mlp_predict/_blend        ensemble mean and relative spread for
+                                   every state;
+  5. eph_scattering_rates          plain rates again at the k points of the
+     + eph_merge_rates             states whose spread exceeds the threshold
+                                   (and the training states), merged in;
+  6. eph_conductivity              sigma from the blended rates.
+The choice of k points (a seeded permutation of the k indices) is host-side
+bookkeeping of which work to do.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class SurrogateResult:
+    inv_tau: "object"          # torch [nt][ns] blended rates
+    sigma: np.ndarray          # [nt][3][3]
+    n_states: int
+    n_train_k: int
+    n_train_states: int
+    n_flagged: int
+    n_fallback_k: int
+    loss: np.ndarray
+    times: dict = field(default_factory=dict)
+    states: tuple = ()         # (k, n, e, v) device tensors
+    raw_inv_tau: "object" = None  # network-only ensemble mean (before fallback)
+
+
+def run(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_frac=0.02, members=5,
+        steps=2000, batch=256, lr=2e-3, threshold=0.01, seed=1649307, precision="fp64", log=None):
+    import torch
+    from .eph import Mlp, merge_rates
+
+    def say(*a):
+        if log:
+            log(*a)
+
+    temps = list(np.atleast_1d(temps))
+    nt = len(temps)
+    times = {}
+    t0 = time.perf_counter()
+    P = lambda ks=None: ctx.params(grid, mu, temps, eta, win_lo, win_hi, band_lo, band_hi, precision=precision,
+                                   k_subset=ks)
+    sk, sn, se, sv = ctx.select_states(P())
+    torch.cuda.synchronize()
+    ns = int(sk.shape[0])
+    times["select_s"] = time.perf_counter() - t0
+    # ---- training set: a seeded fraction of the k points with states ----
+    kall = np.unique(sk.cpu().numpy())
+    rng = np.random.default_rng(seed)
+    ntk = max(1, int(round(train_frac * kall.size)))
+    ktrain = np.sort(rng.choice(kall, size=ntk, replace=False))
+    t1 = time.perf_counter()
+    tr, _ = ctx.scattering_rates(P(ktrain))
+    torch.cuda.synchronize()
+    times["train_rates_s"] = time.perf_counter() - t1
+    say(f"[surrogate] {ns} states, training on {tr.state_k.shape[0]} states at {ntk} k points")
+    # ---- fit ----
+    t2 = time.perf_counter()
+    mlp = Mlp(ctx, members=members, n_out=nt, seed=seed)
+    x_tr, y_tr = mlp.features(tr.state_k, tr.energy, tr.vel, grid, mu, inv_tau=tr.inv_tau)
+    loss = mlp.train(x_tr, y_tr, steps=steps, batch=batch, lr=lr)
+    torch.cuda.synchronize()
+    times["fit_s"] = time.perf_counter() - t2
+    say(f"[surrogate] member losses {np.array2string(loss, precision=4)}")
+    # ---- predict everything, flag disagreement ----
+    t3 = time.perf_counter()
+    x_all, _ = mlp.features(sk, se, sv, grid, mu)
+    y = mlp.predict(x_all)
+    inv_tau, flag, nflag = mlp.blend(y, threshold)
+    raw = inv_tau.clone()
+    torch.cuda.synchronize()
+    times["predict_s"] = time.perf_counter() - t3
+    # ---- fallback: plain rates at the k points of flagged states ----
+    t4 = time.perf_counter()
+    merge_rates(ctx, sk, sn, inv_tau, tr.state_k, tr.state_n, tr.inv_tau)
+    kflag = np.unique(sk[flag.bool()].cpu().numpy()) if nflag else np.zeros(0, np.int64)
+    kflag = np.setdiff1d(kflag, ktrain)
+    if kflag.size:
+        fb, _ = ctx.scattering_rates(P(kflag))
+        merge_rates(ctx, sk, sn, inv_tau, fb.state_k, fb.state_n, fb.inv_tau)
+    torch.cuda.synchronize()
+    times["fallback_s"] = time.perf_counter() - t4
+    say(f"[surrogate] {nflag} states flagged, plain fallback at {kflag.size} k points")
+    sig = ctx.conductivity(se, sv, inv_tau.reshape(-1), mu, temps, grid ** 3)
+    times["total_s"] = time.perf_counter() - t0
+    mlp.close()
+    return SurrogateResult(inv_tau, sig, ns, ntk, int(tr.state_k.shape[0]), nflag, int(kflag.size), loss, times,
+                           (sk, sn, se, sv), raw)

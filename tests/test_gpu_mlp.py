@@ -1,0 +1,106 @@
+"""The surrogate's hand-written MLP kernels against the FP64 reference, and
+the surrogate-with-fallback path against the full plain computation.
+
+Bounds: the FP32 gradient of the loss over 64-128 samples agrees with the FP64
+reference to 1e-4 of its largest component (rounding of 128-term FP32 dot
+products); forward predictions to 1e-4 relative.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import log, params_for, gpu_run, rel_err
+from synth import make_system, workload
+from oracle import mlp as ref
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_16493_amd import Context
+    c = Context(make_system("toy_sc"))
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("nout,members", [(1, 2), (3, 3)])
+def test_gradient_vs_fp64_reference(ctx, nout, members):
+    import torch
+    from paper_2306_16493_amd.eph import Mlp
+    m = Mlp(ctx, members=members, n_out=nout, seed=3)
+    rng = np.random.default_rng(nout)
+    p = (rng.standard_normal((members, m.n_params)) * 0.08).astype(np.float32)
+    m.set_params(p)
+    assert np.array_equal(m.get_params(), p)
+    n = 96
+    x = rng.standard_normal((n, ref.NIN)).astype(np.float32)
+    y = rng.standard_normal((n, nout)).astype(np.float32)
+    dev = torch.device("cuda")
+    loss, g = m.gradient(torch.tensor(x, device=dev), torch.tensor(y, device=dev))
+    for e in range(members):
+        lr_, gr = ref.loss_and_grad(p[e].astype(np.float64), x, y, nout)
+        assert abs(loss[e] - lr_) <= 1e-4 * abs(lr_)
+        err = np.max(np.abs(g[e] - gr)) / np.max(np.abs(gr))
+        log(f"[mlp] member {e}: grad max err {err:.2e}")
+        assert err < 1e-4
+
+
+def test_forward_and_training(ctx):
+    import torch
+    from paper_2306_16493_amd.eph import Mlp
+    m = Mlp(ctx, members=2, n_out=2, seed=5)
+    rng = np.random.default_rng(7)
+    n = 4096
+    x = rng.uniform(-1, 1, (n, ref.NIN)).astype(np.float32)
+    y = np.stack([np.sin(2 * x[:, 0]) + 0.5 * x[:, 3] ** 2, np.cos(x[:, 1] - x[:, 4])], axis=1).astype(np.float32)
+    dev = torch.device("cuda")
+    xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    l0 = m.train(xt, yt, steps=1, batch=256, lr=1e-3)
+    l1 = m.train(xt, yt, steps=1500, batch=256, lr=2e-3)
+    log(f"[mlp] loss {l0} -> {l1}")
+    assert np.all(l1 < 0.05 * l0)
+    # forward pass of the GPU against the reference with the same normalisation
+    pr = m.get_params()
+    xm, xs = x.astype(np.float64).mean(0), x.astype(np.float64).std(0)
+    ym, ys = y.astype(np.float64).mean(0), y.astype(np.float64).std(0)
+    pred = m.predict(xt[:256]).cpu().numpy()
+    for e in range(2):
+        yr, _, _ = ref.forward(pr[e].astype(np.float64), (x[:256] - xm) / xs, 2)
+        yr = yr * ys + ym
+        assert np.max(np.abs(pred[e] - yr)) < 1e-4 * np.max(np.abs(yr)) + 1e-5
+
+
+def test_surrogate_with_fallback_vs_plain():
+    """Al-like 24^3: the ensemble fit on plain rates of a seeded k subset,
+    with plain fallback where the members disagree by more than 1%, gives
+    sigma within 1e-3 of the full plain run; the network alone (no fallback)
+    beats the constant-rate estimate built from the same training rates."""
+    import torch
+    from paper_2306_16493_amd import Context, surrogate
+    w = workload("al_fcc_100", 24)
+    s = make_system(w.system)
+    c = Context(s)
+    mu = s.mu_centroid
+    lo, hi = mu + w.window[0], mu + w.window[1]
+    temps = [300.0]
+    full = gpu_run(c, c.params(24, mu, temps, w.eta, lo, hi))
+    res = full["res"]
+    sig_full = c.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, temps, 24 ** 3)
+    r = surrogate.run(c, 24, mu, temps, w.eta, lo, hi, train_frac=0.25, steps=1500, threshold=0.01, log=log)
+    err = rel_err(r.sigma, sig_full)
+    log(f"[surrogate] sigma rel err {err:.3e}; flagged {r.n_flagged}/{r.n_states}; times {r.times}")
+    assert np.array_equal(r.states[0].cpu().numpy(), full["state_k"])
+    assert err < 1e-3
+    # gain over the method without the network: constant rate = mean training rate
+    sk, sn, se, sv = r.states
+    raw = r.raw_inv_tau.reshape(-1)
+    sig_net = c.conductivity(se, sv, raw, mu, temps, 24 ** 3)
+    it_full = full["inv_tau"][0]
+    const = torch.full_like(raw, float(np.exp(np.mean(np.log(it_full)))))
+    sig_const = c.conductivity(se, sv, const, mu, temps, 24 ** 3)
+    e_net, e_const = rel_err(sig_net, sig_full), rel_err(sig_const, sig_full)
+    log(f"[surrogate] network-only sigma err {e_net:.3e} vs constant-rate {e_const:.3e}")
+    assert e_net < e_const
