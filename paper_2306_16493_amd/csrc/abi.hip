@@ -528,7 +528,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
       EPH_HIP(c, tm.mark(&eb2));
       e_batch.insert(e_batch.end(), {eb0, eb1, eb2});
       c->launches[0]++;
-      c->launches[1]++;
+      c->launches[1] += (gstage == 0 && gwave > 0) ? N : 1;
       g0 = g1;
     }
     EPH_HIP(c, launch_summarize(ns, c->state_cnt.as<int64_t>(), inv_tau_s, ctr + 3, st));
