@@ -30,12 +30,19 @@ struct WaveLayout {
   static constexpr int C = NW * NM;
   static constexpr int SMX = GW + NW;  // member states + shadow states
   static constexpr int NZ = 4;         // Z ring slots (q-lines in flight)
-  __host__ __device__ static size_t z_bytes() { return align16(sizeof(typename V2<T>::t) * NZ * GW * NB * C); }
+  static constexpr int VCAP = 64 + 64 * GW * NW;  // vertex queue: one pass of candidates + a partial pass
+  // one Z block per (slot, state), padded by 16 bytes so that the blocks a
+  // vertex pass reads at the same offset fall in different LDS banks
+  static constexpr int ZB = NB * C + (int)(16 / sizeof(typename V2<T>::t));
+  __host__ __device__ static size_t z_bytes() { return align16(sizeof(typename V2<T>::t) * NZ * GW * ZB); }
   __host__ __device__ static int qcap(int N) { return 64 + SMX * N; }
   __host__ __device__ static size_t q_bytes(int N) { return align16(4 * (size_t)qcap(N)); }
   __host__ __device__ static size_t misc_bytes() { return align16(SMX * 8 + SMX * 4 * 4 + NZ * 8 + 64); }
   __host__ __device__ static size_t line_bytes(int N) { return align16(8 * (size_t)N * NW); }
-  __host__ __device__ static size_t per_wave(int N) { return z_bytes() + q_bytes(N) + misc_bytes() + line_bytes(N); }
+  __host__ __device__ static size_t v_bytes() { return align16(4 * (size_t)VCAP); }
+  __host__ __device__ static size_t per_wave(int N) {
+    return z_bytes() + q_bytes(N) + misc_bytes() + line_bytes(N) + v_bytes();
+  }
   __host__ __device__ static size_t tab_bytes(int N) { return align16(sizeof(typename V2<T>::t) * N); }
   __host__ __device__ static size_t total(int N) { return tab_bytes(N) + 4 * per_wave(N); }
 };
@@ -43,7 +50,7 @@ struct WaveLayout {
 #ifndef EPH_WAVE_OCC
 #define EPH_WAVE_OCC 2
 #endif
-template <class T, int NW, int NM, int GW, int NB, int LPL>
+template <class T, int NW, int NM, int GW, int NB, int LPL, bool VQ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OCC))) void rates_wave_kernel(
     RatesArgs a) {
   using C2 = typename V2<T>::t;
@@ -59,7 +66,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 
   C2 *sTab = reinterpret_cast<C2 *>(smem);
   unsigned char *wb = smem + LY::tab_bytes(N) + (size_t)wave * LY::per_wave(N);
-  C2 *sZ = reinterpret_cast<C2 *>(wb);  // [NZ][GW][NB][C]
+  C2 *sZ = reinterpret_cast<C2 *>(wb);  // [NZ][GW][ZB]: [NB][C] + pad
   uint32_t *sQ = reinterpret_cast<uint32_t *>(wb + LY::z_bytes());
   unsigned char *misc = wb + LY::z_bytes() + LY::q_bytes(N);
   double *sEps = reinterpret_cast<double *>(misc);  // [SMX] state energies
@@ -69,6 +76,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   int *sK1 = sKcnt + SMX;                             // [SMX] k1 of each k-slot
   int *sSlot = sK1 + SMX;                             // [NZ][2] (q2, line) of each Z slot
   double *sLine = reinterpret_cast<double *>(misc + LY::misc_bytes());  // [NW][N] current line energies
+  uint32_t *sV = reinterpret_cast<uint32_t *>(misc + LY::misc_bytes() + LY::line_bytes(N));  // vertex queue
 
   for (int t = threadIdx.x; t < N; t += 256) sTab[t] = mk<T>((T)a.tab[t].x, (T)a.tab[t].y);
   __syncthreads();  // the only workgroup barrier
@@ -119,6 +127,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   }
   NK = __shfl(NK, 0, 64);
   __syncwarp();
+  int KMX = 0;  // most states at one k point of the group (wave-uniform)
+  for (int ks = 0; ks < NK; ks++) KMX = max(KMX, sKcnt[ks]);
 
   double acc[GW][EPH_MAX_TEMPS];
   unsigned nq_s[GW], nt_s[GW];
@@ -147,7 +157,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   // One candidate = (k-slot, p1, Z slot): every state of that k point against
   // every final band m at p = k + q.  drain(n) evaluates the first n queued.
   int qn = 0;
-  auto drain = [&](int count) {
+  auto drain = [&](int count) __attribute__((always_inline)) {
     for (int base = 0; base < count; base += 64) {
       const int i = base + lane;
       if (i >= count) continue;
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 #pragma unroll
           for (int mu = 0; mu < NM; mu++) wr[mu] = wi[mu] = 0;
           int i1 = imod(q1 * lo1, N);
-          const C2 *zs = sZ + ((size_t)zs_slot * GW + s) * NB * C;
+          const C2 *zs = sZ + ((size_t)zs_slot * GW + s) * LY::ZB;
 #pragma unroll 1
           for (int pp = 0; pp < NB; pp++) {
             const C2 ph = sTab[i1];
@@ -255,8 +265,178 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
       if (hit && !(cont && ks == 0)) my_nkq++;
     }
   };
+  // Two-level form: stage1(n) sieves the first n queued candidates against
+  // every (state, final band) pair and appends the pairs with a kept term to
+  // the vertex queue (drained in whole passes after each candidate pass, so
+  // it holds < 64 + 64*GW*NW entries); vdrain(n) evaluates the first n
+  // vertices, one per lane.
+  // Vertex item: p1 | s << 10 | m << 13 | zslot << 16 | vp << 18 | vm << 24.
+  int vn = 0;
+  auto vdrain = [&](int count) __attribute__((always_inline)) {
+    for (int base = 0; base < count; base += 64) {
+      const int i = base + lane;
+      if (i >= count) continue;
+      const uint32_t it = sV[i];
+      const int p1 = (int)(it & 1023u), s = (int)((it >> 10) & 7u), m = (int)((it >> 13) & 7u);
+      const int zs_slot = (int)((it >> 16) & 3u);
+      const unsigned vp = (it >> 18) & 63u, vm = (it >> 24) & 63u;
+      const int ks = sKs[s];
+      const int line = sSlot[2 * zs_slot + 1], q2 = sSlot[2 * zs_slot];
+      int q1 = p1 - sK1[ks];
+      q1 += (q1 < 0) ? N : 0;
+      const int64_t qidx = q1 + (int64_t)N * (q2 + (int64_t)N * a.q3_cur);
+      const int64_t pidx = p1 + (int64_t)N * line;
+      const double es = sEps[s];
+      const double epm = a.eps[pidx * NW + m];
+      my_nv++;
+      C2 vrow[NW];
+#pragma unroll
+      for (int i2 = 0; i2 < NW; i2++) {
+        if constexpr (sizeof(T) == 8) vrow[i2] = a.evec[(pidx * NW + m) * NW + i2];
+        else vrow[i2] = a.evec32[(pidx * NW + m) * NW + i2];
+      }
+      T wr[NM], wi[NM];
+#pragma unroll
+      for (int mu = 0; mu < NM; mu++) wr[mu] = wi[mu] = 0;
+      // phases e^{i 2pi q1 p1'/N}, p1' = lo1 .. lo1 + NB - 1, by recurrence from
+      // two table entries (per-lane table lookups would conflict in LDS banks)
+      C2 ph = sTab[imod(q1 * lo1, N)];
+      const C2 rq = sTab[q1];
+      const C2 *zs = sZ + ((size_t)zs_slot * GW + s) * LY::ZB;
+#pragma unroll 1
+      for (int pp = 0; pp < NB; pp++) {
+#pragma unroll
+        for (int mu = 0; mu < NM; mu++) {
+          T tr = 0, ti = 0;
+#pragma unroll
+          for (int i2 = 0; i2 < NW; i2++) {
+            const C2 z = zs[pp * C + mu * NW + i2];
+            cmac_conj<T>(tr, ti, vrow[i2].x, vrow[i2].y, z.x, z.y);
+          }
+          cmac<T>(wr[mu], wi[mu], ph.x, ph.y, tr, ti);
+        }
+        ph = mk<T>(fma(ph.x, rq.x, -ph.y * rq.y), fma(ph.x, rq.y, ph.y * rq.x));
+      }
+      // occupations: indices clamped to the last temperature, so the loads
+      // need no branch (entries t >= nt are never used)
+      double fo[EPH_MAX_TEMPS];
+#pragma unroll
+      for (int t = 0; t < EPH_MAX_TEMPS; t++) fo[t] = a.occ_f[(pidx * NW + m) * nt + min(t, nt - 1)];
+      double contrib[EPH_MAX_TEMPS];
+#pragma unroll
+      for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = 0.0;
+#pragma unroll
+      for (int nu = 0; nu < NM; nu++) {
+        const bool okp = (vp >> nu) & 1u, okm = (vm >> nu) & 1u;
+        if (!(okp || okm)) continue;
+        const double omv = a.om[qidx * NM + nu];
+        T gr = 0, gi = 0;
+#pragma unroll
+        for (int mu = 0; mu < NM; mu++) {
+          C2 u;
+          if constexpr (sizeof(T) == 8) u = a.uu[(qidx * NM + nu) * NM + mu];
+          else u = a.uu32[(qidx * NM + nu) * NM + mu];
+          cmac<T>(gr, gi, wr[mu], wi[mu], u.x, u.y);
+        }
+        const double g2 = fma((double)gr, (double)gr, (double)gi * (double)gi);
+        const double xp = es + omv - epm, xm = es - omv - epm;
+        const double dp = okp ? exp(-(xp * inv_eta) * (xp * inv_eta)) * dnorm : 0.0;
+        const double dm = okm ? exp(-(xm * inv_eta) * (xm * inv_eta)) * dnorm : 0.0;
+#pragma unroll
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) {
+          const double nq = a.occ_n[(qidx * NM + nu) * nt + min(t, nt - 1)];
+          contrib[t] = fma(g2, fma(nq + fo[t], dp, (1.0 + nq - fo[t]) * dm), contrib[t]);
+        }
+      }
+#pragma unroll
+      for (int ss = 0; ss < GW; ss++) {
+        const bool me = ss == s;
+#pragma unroll
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) acc[ss][t] += me ? contrib[t] : 0.0;
+      }
+    }
+  };
+  auto vpop = [&](int n) __attribute__((always_inline)) {
+    const int rem = vn - n;
+    for (int b = 0; b < rem; b += 64) {
+      const uint32_t v = (b + lane < rem) ? sV[n + b + lane] : 0u;
+      __syncwarp();
+      if (b + lane < rem) sV[b + lane] = v;
+      __syncwarp();
+    }
+    vn = rem;
+  };
+  auto stage1 = [&](int count) __attribute__((always_inline)) {
+    for (int base = 0; base < count; base += 64) {
+      const int i = base + lane;
+      const bool act = i < count;
+      const uint32_t it = act ? sQ[i] : 0u;
+      const int p1 = (int)(it & 1023u), ks = (int)((it >> 10) & 31u), zs_slot = (int)(it >> 15);
+      const int line = sSlot[2 * zs_slot + 1], q2 = sSlot[2 * zs_slot];
+      int q1 = p1 - sK1[ks];
+      q1 += (q1 < 0) ? N : 0;
+      const int64_t qidx = q1 + (int64_t)N * (q2 + (int64_t)N * a.q3_cur);
+      const int64_t pidx = p1 + (int64_t)N * line;
+      double om[NM], ep[NW];
+#pragma unroll
+      for (int nu = 0; nu < NM; nu++) om[nu] = act ? a.om[qidx * NM + nu] : 0.0;
+#pragma unroll
+      for (int m = 0; m < NW; m++) ep[m] = act ? a.eps[pidx * NW + m] : 0.0;
+      const int sf = sKfirst[ks], sc = act ? sKcnt[ks] : 0;
+      double esr[NW];
+#pragma unroll
+      for (int j = 0; j < NW; j++) esr[j] = (j < sc) ? sEps[sf + j] : 0.0;
+      bool hit = false;
+#pragma unroll
+      for (int j = 0; j < NW; j++) {
+        if (j >= KMX) break;  // wave-uniform
+        const int s = sf + j;
+        const bool sv = j < sc;
+        const double es = esr[j];
+        bool hit_s = false;
+        unsigned nterm = 0;
+#pragma unroll
+        for (int m = 0; m < NW; m++) {
+          unsigned vp = 0, vm = 0;
+#pragma unroll
+          for (int nu = 0; nu < NM; nu++) {
+            const bool okw = sv && om[nu] >= a.wcut;
+            vp |= (okw && fabs(es + om[nu] - ep[m]) <= cut) ? (1u << nu) : 0u;
+            vm |= (okw && fabs(es - om[nu] - ep[m]) <= cut) ? (1u << nu) : 0u;
+          }
+          const bool any = (vp | vm) != 0u;
+          hit_s |= any;
+          nterm += (unsigned)(__popc(vp) + __popc(vm));
+          const bool push = any && s < S;
+          const unsigned long long bits = __ballot(push);
+          if (push)
+            sV[vn + __popcll(bits & ((1ull << lane) - 1ull))] =
+                (uint32_t)p1 | ((uint32_t)s << 10) | ((uint32_t)m << 13) | ((uint32_t)zs_slot << 16) |
+                (vp << 18) | (vm << 24);
+          vn += __popcll(bits);
+        }
+        hit = hit || hit_s;
+        // branch-free per-slot updates (a select on s would become a
+        // dynamically indexed private array)
+#pragma unroll
+        for (int ss = 0; ss < GW; ss++) {
+          const bool me = (ss == s) && sv;
+          nq_s[ss] += (me && hit_s) ? 1u : 0u;
+          nt_s[ss] += me ? nterm : 0u;
+        }
+      }
+      if (act && hit && !(cont && ks == 0)) my_nkq++;
+      __syncwarp();
+      if (vn >= 64) {  // keep the vertex queue below one pass before the next candidates
+        const int vf = vn & ~63;
+        vdrain(vf);
+        __syncwarp();
+        vpop(vf);
+      }
+    }
+  };
   // drop the first n entries of the queue (after they were evaluated)
-  auto pop = [&](int n) {
+  auto pop = [&](int n) __attribute__((always_inline)) {
     const int rem = qn - n;
     for (int b = 0; b < rem; b += 64) {
       const uint32_t v = (b + lane < rem) ? sQ[n + b + lane] : 0u;
@@ -298,6 +478,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
     }
     const int p3line = (k3 + q3 >= N) ? k3 + q3 - N : k3 + q3;
     for (int q2 = 0; q2 < N; q2++, ql++) {
+      const int zslot = ql & (NZ - 1);
+      {  // the Z slot is reused: evaluate queued work that still points at it
+        bool stale = false;
+        for (int b = 0; b < qn; b += 64)
+          stale |= (b + lane < qn) && (int)(sQ[b + lane] >> 15) == zslot;
+        if constexpr (VQ) {
+          for (int b = 0; b < vn; b += 64)
+            stale |= (b + lane < vn) && (int)((sV[b + lane] >> 16) & 3u) == zslot;
+        }
+        if (__any(stale)) {
+          if constexpr (VQ) {
+            stage1(qn);
+            __syncwarp();
+            qn = 0;
+            vdrain(vn);
+            __syncwarp();
+            vn = 0;
+          } else {
+            drain(qn);
+            __syncwarp();
+            qn = 0;
+          }
+        }
+      }
       {  // issue the loads of the next q-line's energies
         int nq2 = q2 + 1, nq3 = q3;
         if (nq2 == N) {
@@ -313,17 +517,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
           nxt[i] = (e < LN) ? ln[e] : 0.0;
         }
       }
-      const int zslot = ql & (NZ - 1);
-      {  // the Z slot is reused: evaluate queued candidates that still point at it
-        bool stale = false;
-        for (int b = 0; b < qn; b += 64)
-          stale |= (b + lane < qn) && (int)(sQ[b + lane] >> 15) == zslot;
-        if (__any(stale)) {
-          drain(qn);
-          __syncwarp();
-          qn = 0;
-        }
-      }
       // ---- Z_s(p1; q2, q3) -> LDS slot ----
       C2 ph2[NB];
       {
@@ -335,7 +528,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
           i2 -= (i2 >= N) ? N : 0;
         }
       }
-      C2 *zslot_base = sZ + (size_t)zslot * GW * NB * C;
+      C2 *zslot_base = sZ + (size_t)zslot * GW * LY::ZB;
 #pragma unroll
       for (int j = 0; j < NPAIR; j++) {
         const int P = lane + 64 * j;
@@ -343,7 +536,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
           T r = 0, i = 0;
 #pragma unroll
           for (int p2 = 0; p2 < NB; p2++) cmac<T>(r, i, ph2[p2].x, ph2[p2].y, yr[j][p2], yi[j][p2]);
-          zslot_base[P] = mk<T>(r, i);
+          zslot_base[(P / (NB * C)) * LY::ZB + P % (NB * C)] = mk<T>(r, i);
         }
       }
       const int p2line = (k2 + q2 >= N) ? k2 + q2 - N : k2 + q2;
@@ -356,15 +549,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
       // ---- candidates of this q-line: (k-slot, p1) with some band in the window ----
       for (int ks = 0; ks < NK; ks++) {
         const int sf = sKfirst[ks], sc = sKcnt[ks];
+        double esr[NW];  // energies of the k-slot's states; unused slots never match
+#pragma unroll
+        for (int j = 0; j < NW; j++) esr[j] = (j < sc) ? sEps[sf + j] : 1e300;
         for (int c0 = 0; c0 < N; c0 += 64) {
           const int p1 = c0 + lane;
           bool any = false;
           if (p1 < N) {
+            double ev[NW];
 #pragma unroll
-            for (int m = 0; m < NW; m++) {
-              const double ev = sLine[m * N + p1];
-              for (int s = sf; s < sf + sc; s++) any |= fabs(ev - sEps[s]) <= W;
-            }
+            for (int m = 0; m < NW; m++) ev[m] = sLine[m * N + p1];
+#pragma unroll
+            for (int m = 0; m < NW; m++)
+#pragma unroll
+              for (int j = 0; j < NW; j++) any |= fabs(ev[m] - esr[j]) <= W;
           }
           const unsigned long long bits = __ballot(any);
           if (any) sQ[qn + __popcll(bits & ((1ull << lane) - 1ull))] =
@@ -373,22 +571,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
         }
       }
       __syncwarp();
-      if (qn >= 64) {  // evaluate whole passes only; the rest waits for later q-lines
-        const int full = qn & ~63;
-        drain(full);
-        __syncwarp();
-        pop(full);
-      }
-      // stage the next line's energies ([m][p1] in LDS)
+      // stage the next line's energies ([m][p1] in LDS); the scan of this
+      // line is done, and the drains below read energies from global memory
 #pragma unroll
       for (int i = 0; i < LPL; i++) {
         const int e = lane + 64 * i;
         if (e < LN) sLine[(e % NW) * N + e / NW] = nxt[i];
       }
       __syncwarp();
+      if (qn >= 64) {  // evaluate whole passes only; the rest waits for later q-lines
+        const int full = qn & ~63;
+        if constexpr (VQ) {
+          stage1(full);
+          __syncwarp();
+          pop(full);
+        } else {
+          drain(full);
+          __syncwarp();
+          pop(full);
+        }
+      }
     }
   }
-  drain(qn);
+  if constexpr (VQ) {
+    stage1(qn);
+    __syncwarp();
+    vdrain(vn);
+  } else {
+    drain(qn);
+  }
 
   // ---- fixed-order reductions; q3 slabs add up in launch order ----
 #pragma unroll
@@ -427,12 +638,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   }
 }
 
+#ifndef EPH_WAVE_VQ
+#define EPH_WAVE_VQ 1
+#endif
 template <class T, int NW, int NM, int GW, int NB, int LPL>
 hipError_t launch_wave_l(const RatesArgs &a, hipStream_t st) {
   using LY = WaveLayout<T, NW, NM, GW, NB>;
   const size_t sh = LY::total(a.N);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL>;
+  auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL, EPH_WAVE_VQ != 0>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
   const int64_t nblk = (a.ng + 3) / 4;
