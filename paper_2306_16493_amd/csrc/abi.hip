@@ -401,7 +401,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     const bool allow_stage = ks == "stage", allow_wave = ks.empty() || ks == "wave";
     const int gstage =
         (allow_stage && p->precision == EPH_FP64) ? rates_stage_group(nw, nm, c->box, N, p->n_temps) : 0;
-    const int gwave = (gstage > 0 || !allow_wave) ? 0 : rates_wave_group(nw, nm, c->box, N);
+    const int gwave = (gstage > 0 || !allow_wave) ? 0 : rates_wave_group(nw, nm, c->box, N, p->precision);
     const int gmax = gstage > 0 ? gstage : gwave > 0 ? gwave : rates_group_max(nw, nm);
     EPH_HIP(c, c->grp_tmp.ensure(sizeof(int64_t) * 2 * (ns + 1)));
     int64_t *flag = c->grp_tmp.as<int64_t>(), *pos = flag + ns + 1;
@@ -428,15 +428,15 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     } else {
       double kts[EPH_MAX_TEMPS];
       for (int t = 0; t < p->n_temps; t++) kts[t] = U.kb_evk * p->temps_K[t];
-      EPH_HIP(c, c->occ.ensure(sizeof(double) * NQ * (nw + nm) * p->n_temps));
+      EPH_HIP(c, c->occ.ensure(sizeof(double) * NQ * (nw + nm) * EPH_MAX_TEMPS));
       EPH_HIP(c, launch_occupations(NQ, nw, nm, c->eps.as<double>(), c->om.as<double>(), p->mu_eV, p->n_temps, kts,
                                     p->omega_cut_eV, c->occ.as<double>(),
-                                    c->occ.as<double>() + (size_t)NQ * nw * p->n_temps, st));
+                                    c->occ.as<double>() + (size_t)NQ * nw * EPH_MAX_TEMPS, st));
       if (gstage > 0) {
         EPH_HIP(c, c->packed.ensure(sizeof(double) * stage_table_words(NQ, nw, nm, p->n_temps)));
         EPH_HIP(c, launch_pack_tables(NQ, nw, nm, p->n_temps, c->eps.as<double>(), c->om.as<double>(),
                                       c->evec.as<double2>(), c->uu.as<double2>(), c->occ.as<double>(),
-                                      c->occ.as<double>() + (size_t)NQ * nw * p->n_temps, c->packed.as<double>(),
+                                      c->occ.as<double>() + (size_t)NQ * nw * EPH_MAX_TEMPS, c->packed.as<double>(),
                                       c->packed.as<double>() + stage_table_words(NQ, 0, nm, p->n_temps), st));
       }
     }
@@ -484,7 +484,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     a.evec32 = fp32 ? c->evec32.as<float2>() : nullptr;
     a.uu32 = fp32 ? c->uu32.as<float2>() : nullptr;
     a.occ_f = c->occ.as<double>();
-    a.occ_n = c->occ.as<double>() + (size_t)NQ * nw * p->n_temps;
+    a.occ_n = c->occ.as<double>() + (size_t)NQ * nw * EPH_MAX_TEMPS;
     const int ncol = c->box.count() * nm * nw;
     int64_t g0 = 0;
     while (g0 < ng) {

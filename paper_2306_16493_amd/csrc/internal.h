@@ -160,15 +160,15 @@ struct RatesArgs {
   int64_t *st_counts;              // [ns_total][2]: n_q_valid, n_terms
   unsigned long long *n_kq;
   unsigned long long *n_vertex;
-  const double *occ_f;             // [N^3][nw][nt] Fermi factors (wave kernel)
-  const double *occ_n;             // [N^3][nm][nt] Bose factors, 0 below omega_cut
+  const double *occ_f;             // [N^3][nw][EPH_MAX_TEMPS] Fermi factors (wave kernel)
+  const double *occ_n;             // [N^3][nm][EPH_MAX_TEMPS] Bose factors, 0 below omega_cut
   int q3_lo, q3_hi;                // q3 planes of this launch (wave kernel)
   int q3_cur;                      // the plane (wave kernel launches one plane at a time)
 };
 hipError_t launch_rates(int precision, const RatesArgs &a, hipStream_t st);
 // Wave-autonomous rate kernel; rates_wave_group gives its states per group
 // (0 when the shape is not served and launch_rates must be used).
-int rates_wave_group(int nw, int nm, RpBox box, int N);
+int rates_wave_group(int nw, int nm, RpBox box, int N, int precision);
 hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st);
 // Staged q-line rate kernel (FP64): states per group, 0 when not served.
 int rates_stage_group(int nw, int nm, RpBox box, int N, int nt);

@@ -431,7 +431,7 @@ __global__ void pack_tables_kernel(int64_t nq, int nw, int nm, int nt, const dou
   const int QR = qrec(nm, nt), PR = prec(nw, nt);
   double *r = qt + q * QR;
   for (int nu = 0; nu < nm; nu++) r[nu] = om[q * nm + nu];
-  for (int x = 0; x < nm * nt; x++) r[nm + x] = occ_n[q * nm * nt + x];
+  for (int x = 0; x < nm * nt; x++) r[nm + x] = occ_n[(q * nm + x / nt) * EPH_MAX_TEMPS + x % nt];
   const int ou = qoff_u(nm, nt), ov = poff_v(nt);
   for (int x = nm + nm * nt; x < ou; x++) r[x] = 0.0;
   for (int x = 0; x < nm * nm; x++) {
@@ -441,7 +441,7 @@ __global__ void pack_tables_kernel(int64_t nq, int nw, int nm, int nt, const dou
   for (int m = 0; m < nw; m++) {
     double *p = pt + (q * nw + m) * PR;
     p[0] = eps[q * nw + m];
-    for (int t = 0; t < nt; t++) p[1 + t] = occ_f[(q * nw + m) * nt + t];
+    for (int t = 0; t < nt; t++) p[1 + t] = occ_f[(q * nw + m) * EPH_MAX_TEMPS + t];
     for (int x = 1 + nt; x < ov; x++) p[x] = 0.0;
     for (int i = 0; i < nw; i++) {
       p[ov + 2 * i] = evec[(q * nw + m) * nw + i].x;

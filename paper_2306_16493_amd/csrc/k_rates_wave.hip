@@ -35,11 +35,11 @@ struct WaveLayout {
   // vertex pass reads at the same offset fall in different LDS banks
   static constexpr int ZB = NB * C + (int)(16 / sizeof(typename V2<T>::t));
   __host__ __device__ static size_t z_bytes() { return align16(sizeof(typename V2<T>::t) * NZ * GW * ZB); }
-  __host__ __device__ static int qcap(int N) { return 64 + SMX * N; }
+  __host__ __device__ static int qcap(int) { return 128; }  // drained in whole passes during the scan
   __host__ __device__ static size_t q_bytes(int N) { return align16(4 * (size_t)qcap(N)); }
   __host__ __device__ static size_t misc_bytes() { return align16(SMX * 8 + SMX * 4 * 4 + NZ * 8 + 64); }
   __host__ __device__ static size_t line_bytes(int N) { return align16(8 * (size_t)N * NW); }
-  __host__ __device__ static size_t v_bytes() { return align16(4 * (size_t)VCAP); }
+  __host__ __device__ static size_t v_bytes() { return align16(8 * (size_t)VCAP); }
   __host__ __device__ static size_t per_wave(int N) {
     return z_bytes() + q_bytes(N) + misc_bytes() + line_bytes(N) + v_bytes();
   }
@@ -50,7 +50,7 @@ struct WaveLayout {
 #ifndef EPH_WAVE_OCC
 #define EPH_WAVE_OCC 2
 #endif
-template <class T, int NW, int NM, int GW, int NB, int LPL, bool VQ>
+template <class T, int NW, int NM, int GW, int NB, int LPL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OCC))) void rates_wave_kernel(
     RatesArgs a) {
   using C2 = typename V2<T>::t;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   int *sK1 = sKcnt + SMX;                             // [SMX] k1 of each k-slot
   int *sSlot = sK1 + SMX;                             // [NZ][2] (q2, line) of each Z slot
   double *sLine = reinterpret_cast<double *>(misc + LY::misc_bytes());  // [NW][N] current line energies
-  uint32_t *sV = reinterpret_cast<uint32_t *>(misc + LY::misc_bytes() + LY::line_bytes(N));  // vertex queue
+  uint2 *sV = reinterpret_cast<uint2 *>(misc + LY::misc_bytes() + LY::line_bytes(N));  // vertex queue
 
   for (int t = threadIdx.x; t < N; t += 256) sTab[t] = mk<T>((T)a.tab[t].x, (T)a.tab[t].y);
   __syncthreads();  // the only workgroup barrier
@@ -129,6 +129,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   __syncwarp();
   int KMX = 0;  // most states at one k point of the group (wave-uniform)
   for (int ks = 0; ks < NK; ks++) KMX = max(KMX, sKcnt[ks]);
+  double esm[GW];  // energies of the member states (wave-uniform)
+#pragma unroll
+  for (int ss = 0; ss < GW; ss++) esm[ss] = sEps[min(ss, S - 1)];
 
   double acc[GW][EPH_MAX_TEMPS];
   unsigned nq_s[GW], nt_s[GW];
@@ -155,139 +158,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   }
 
   // One candidate = (k-slot, p1, Z slot): every state of that k point against
-  // every final band m at p = k + q.  drain(n) evaluates the first n queued.
+  // every final band m at p = k + q.
   int qn = 0;
-  auto drain = [&](int count) __attribute__((always_inline)) {
-    for (int base = 0; base < count; base += 64) {
-      const int i = base + lane;
-      if (i >= count) continue;
-      const uint32_t it = sQ[i];
-      const int p1 = (int)(it & 1023u), ks = (int)((it >> 10) & 31u), zs_slot = (int)(it >> 15);
-      const int q2 = sSlot[2 * zs_slot], line = sSlot[2 * zs_slot + 1];
-      int q1 = p1 - sK1[ks];
-      q1 += (q1 < 0) ? N : 0;
-      const int q3 = a.q3_cur;
-      const int64_t qidx = q1 + (int64_t)N * (q2 + (int64_t)N * q3);
-      const int64_t pidx = p1 + (int64_t)N * line;
-      double om[NM];
-#pragma unroll
-      for (int nu = 0; nu < NM; nu++) om[nu] = a.om[qidx * NM + nu];
-      bool hit = false;
-      const int sf = sKfirst[ks], sc = sKcnt[ks];
-      for (int s = sf; s < sf + sc; s++) {
-        const double es = sEps[s];
-        bool hit_s = false;
-        int nterm = 0;
-        double contrib[EPH_MAX_TEMPS];
-#pragma unroll
-        for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = 0.0;
-#pragma unroll 1
-        for (int m = 0; m < NW; m++) {
-          const double epm = a.eps[pidx * NW + m];
-          unsigned vp = 0, vm = 0;
-#pragma unroll
-          for (int nu = 0; nu < NM; nu++) {
-            const bool okw = om[nu] >= a.wcut;
-            vp |= (okw && fabs(es + om[nu] - epm) <= cut) ? (1u << nu) : 0u;
-            vm |= (okw && fabs(es - om[nu] - epm) <= cut) ? (1u << nu) : 0u;
-          }
-          if ((vp | vm) == 0u) continue;
-          hit_s = true;
-          if (s >= S) continue;  // shadow state: counted, not computed
-          my_nv++;
-          C2 vrow[NW];
-#pragma unroll
-          for (int i2 = 0; i2 < NW; i2++) {
-            if constexpr (sizeof(T) == 8) vrow[i2] = a.evec[(pidx * NW + m) * NW + i2];
-            else vrow[i2] = a.evec32[(pidx * NW + m) * NW + i2];
-          }
-          // W_mu = sum_p1' e^{i 2pi q1 p1'/N} sum_i conj(V_im(p)) Z_s(p1'; mu, i)
-          T wr[NM], wi[NM];
-#pragma unroll
-          for (int mu = 0; mu < NM; mu++) wr[mu] = wi[mu] = 0;
-          int i1 = imod(q1 * lo1, N);
-          const C2 *zs = sZ + ((size_t)zs_slot * GW + s) * LY::ZB;
-#pragma unroll 1
-          for (int pp = 0; pp < NB; pp++) {
-            const C2 ph = sTab[i1];
-            i1 += q1;
-            i1 -= (i1 >= N) ? N : 0;
-#pragma unroll
-            for (int mu = 0; mu < NM; mu++) {
-              T tr = 0, ti = 0;
-#pragma unroll
-              for (int i2 = 0; i2 < NW; i2++) {
-                const C2 z = zs[pp * C + mu * NW + i2];
-                cmac_conj<T>(tr, ti, vrow[i2].x, vrow[i2].y, z.x, z.y);
-              }
-              cmac<T>(wr[mu], wi[mu], ph.x, ph.y, tr, ti);
-            }
-          }
-          double fo[EPH_MAX_TEMPS];
-#pragma unroll
-          for (int t = 0; t < EPH_MAX_TEMPS; t++) fo[t] = (t < nt) ? a.occ_f[(pidx * NW + m) * nt + t] : 0.0;
-#pragma unroll
-          for (int nu = 0; nu < NM; nu++) {
-            const bool okp = (vp >> nu) & 1u, okm = (vm >> nu) & 1u;
-            if (!(okp || okm)) continue;
-            T gr = 0, gi = 0;
-#pragma unroll
-            for (int mu = 0; mu < NM; mu++) {
-              C2 u;
-              if constexpr (sizeof(T) == 8) u = a.uu[(qidx * NM + nu) * NM + mu];
-              else u = a.uu32[(qidx * NM + nu) * NM + mu];
-              cmac<T>(gr, gi, wr[mu], wi[mu], u.x, u.y);
-            }
-            const double g2 = fma((double)gr, (double)gr, (double)gi * (double)gi);
-            const double xp = es + om[nu] - epm, xm = es - om[nu] - epm;
-            const double dp = okp ? exp(-(xp * inv_eta) * (xp * inv_eta)) * dnorm : 0.0;
-            const double dm = okm ? exp(-(xm * inv_eta) * (xm * inv_eta)) * dnorm : 0.0;
-            nterm += (int)okp + (int)okm;
-#pragma unroll
-            for (int t = 0; t < EPH_MAX_TEMPS; t++) {
-              if (t < nt) {
-                const double nq = a.occ_n[(qidx * NM + nu) * nt + t];
-                contrib[t] = fma(g2, fma(nq + fo[t], dp, (1.0 + nq - fo[t]) * dm), contrib[t]);
-              }
-            }
-          }
-        }
-        hit = hit || hit_s;
-#pragma unroll
-        for (int ss = 0; ss < GW; ss++)
-          if (ss == s) {
-#pragma unroll
-            for (int t = 0; t < EPH_MAX_TEMPS; t++) acc[ss][t] += contrib[t];
-            nq_s[ss] += hit_s ? 1u : 0u;
-            nt_s[ss] += (unsigned)nterm;
-          }
-      }
-      if (hit && !(cont && ks == 0)) my_nkq++;
-    }
-  };
   // Two-level form: stage1(n) sieves the first n queued candidates against
   // every (state, final band) pair and appends the pairs with a kept term to
   // the vertex queue (drained in whole passes after each candidate pass, so
   // it holds < 64 + 64*GW*NW entries); vdrain(n) evaluates the first n
   // vertices, one per lane.
-  // Vertex item: p1 | s << 10 | m << 13 | zslot << 16 | vp << 18 | vm << 24.
+  // Vertex item (64 bits): x = p1 | q1 << 10 | i1 << 20 | zslot << 30 with
+  // i1 = q1*lo1 mod N the first phase index; y = s | m << 3 | vp << 6 |
+  // vm << 12 | q2 << 18.
   int vn = 0;
   auto vdrain = [&](int count) __attribute__((always_inline)) {
     for (int base = 0; base < count; base += 64) {
       const int i = base + lane;
       if (i >= count) continue;
-      const uint32_t it = sV[i];
-      const int p1 = (int)(it & 1023u), s = (int)((it >> 10) & 7u), m = (int)((it >> 13) & 7u);
-      const int zs_slot = (int)((it >> 16) & 3u);
-      const unsigned vp = (it >> 18) & 63u, vm = (it >> 24) & 63u;
-      const int ks = sKs[s];
-      const int line = sSlot[2 * zs_slot + 1], q2 = sSlot[2 * zs_slot];
-      int q1 = p1 - sK1[ks];
-      q1 += (q1 < 0) ? N : 0;
+      // everything the vertex needs is in its queue item (no table lookups)
+      const uint2 it = sV[i];
+      const int p1 = (int)(it.x & 1023u), q1 = (int)((it.x >> 10) & 1023u), i1 = (int)((it.x >> 20) & 1023u);
+      const int zs_slot = (int)(it.x >> 30);
+      const int s = (int)(it.y & 7u), m = (int)((it.y >> 3) & 7u);
+      const unsigned vp = (it.y >> 6) & 63u, vm = (it.y >> 12) & 63u;
+      const int q2 = (int)((it.y >> 18) & 1023u);
+      const int p2l = (k2 + q2 >= N) ? k2 + q2 - N : k2 + q2;
+      const int p3l = (k3 + a.q3_cur >= N) ? k3 + a.q3_cur - N : k3 + a.q3_cur;
       const int64_t qidx = q1 + (int64_t)N * (q2 + (int64_t)N * a.q3_cur);
-      const int64_t pidx = p1 + (int64_t)N * line;
-      const double es = sEps[s];
+      const int64_t pidx = p1 + (int64_t)N * (p2l + (int64_t)N * p3l);
+      double es = esm[0];
+#pragma unroll
+      for (int ss = 1; ss < GW; ss++) es = (s == ss) ? esm[ss] : es;
       const double epm = a.eps[pidx * NW + m];
+      double omq[NM];
+#pragma unroll
+      for (int nu = 0; nu < NM; nu++) omq[nu] = a.om[qidx * NM + nu];
       my_nv++;
       C2 vrow[NW];
 #pragma unroll
@@ -300,7 +203,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
       for (int mu = 0; mu < NM; mu++) wr[mu] = wi[mu] = 0;
       // phases e^{i 2pi q1 p1'/N}, p1' = lo1 .. lo1 + NB - 1, by recurrence from
       // two table entries (per-lane table lookups would conflict in LDS banks)
-      C2 ph = sTab[imod(q1 * lo1, N)];
+      C2 ph = sTab[i1];
       const C2 rq = sTab[q1];
       const C2 *zs = sZ + ((size_t)zs_slot * GW + s) * LY::ZB;
 #pragma unroll 1
@@ -317,35 +220,83 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
         }
         ph = mk<T>(fma(ph.x, rq.x, -ph.y * rq.y), fma(ph.x, rq.y, ph.y * rq.x));
       }
-      // occupations: indices clamped to the last temperature, so the loads
-      // need no branch (entries t >= nt are never used)
-      double fo[EPH_MAX_TEMPS];
-#pragma unroll
-      for (int t = 0; t < EPH_MAX_TEMPS; t++) fo[t] = a.occ_f[(pidx * NW + m) * nt + min(t, nt - 1)];
       double contrib[EPH_MAX_TEMPS];
+      if constexpr (sizeof(T) == 8) {
+        // FP64: the q-side data is loaded mode by mode (a single batch does not
+        // fit the registers next to Y); occupation rows are padded to
+        // EPH_MAX_TEMPS and padding is never accumulated into a written rate
+        double fo[EPH_MAX_TEMPS];
 #pragma unroll
-      for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = 0.0;
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) fo[t] = a.occ_f[(pidx * NW + m) * EPH_MAX_TEMPS + t];
 #pragma unroll
-      for (int nu = 0; nu < NM; nu++) {
-        const bool okp = (vp >> nu) & 1u, okm = (vm >> nu) & 1u;
-        if (!(okp || okm)) continue;
-        const double omv = a.om[qidx * NM + nu];
-        T gr = 0, gi = 0;
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = 0.0;
 #pragma unroll
-        for (int mu = 0; mu < NM; mu++) {
-          C2 u;
-          if constexpr (sizeof(T) == 8) u = a.uu[(qidx * NM + nu) * NM + mu];
-          else u = a.uu32[(qidx * NM + nu) * NM + mu];
-          cmac<T>(gr, gi, wr[mu], wi[mu], u.x, u.y);
+        for (int nu = 0; nu < NM; nu++) {
+          const bool okp = (vp >> nu) & 1u, okm = (vm >> nu) & 1u;
+          if (!(okp || okm)) continue;
+          T gr = 0, gi = 0;
+#pragma unroll
+          for (int mu = 0; mu < NM; mu++) {
+            const C2 u = a.uu[(qidx * NM + nu) * NM + mu];
+            cmac<T>(gr, gi, wr[mu], wi[mu], u.x, u.y);
+          }
+          const double g2 = fma((double)gr, (double)gr, (double)gi * (double)gi);
+          const double xp = es + omq[nu] - epm, xm = es - omq[nu] - epm;
+          const double dp = okp ? exp(-(xp * inv_eta) * (xp * inv_eta)) * dnorm : 0.0;
+          const double dm = okm ? exp(-(xm * inv_eta) * (xm * inv_eta)) * dnorm : 0.0;
+#pragma unroll
+          for (int t = 0; t < EPH_MAX_TEMPS; t++) {
+            const double nq = a.occ_n[(qidx * NM + nu) * EPH_MAX_TEMPS + t];
+            contrib[t] = fma(g2, fma(nq + fo[t], dp, (1.0 + nq - fo[t]) * dm), contrib[t]);
+          }
         }
-        const double g2 = fma((double)gr, (double)gr, (double)gi * (double)gi);
-        const double xp = es + omv - epm, xm = es - omv - epm;
-        const double dp = okp ? exp(-(xp * inv_eta) * (xp * inv_eta)) * dnorm : 0.0;
-        const double dm = okm ? exp(-(xm * inv_eta) * (xm * inv_eta)) * dnorm : 0.0;
+      } else {
+        // FP32: the q-side data of every mode and the Fermi factors, in one
+        // batch of loads (occupation rows are padded to EPH_MAX_TEMPS; padding is never
+        // accumulated into a written rate)
+        static_assert(EPH_MAX_TEMPS == 4, "occupation rows are read as two double2");
+        C2 uq[NM][NM];
+        double nqv[NM][EPH_MAX_TEMPS], fo[EPH_MAX_TEMPS];
 #pragma unroll
-        for (int t = 0; t < EPH_MAX_TEMPS; t++) {
-          const double nq = a.occ_n[(qidx * NM + nu) * nt + min(t, nt - 1)];
-          contrib[t] = fma(g2, fma(nq + fo[t], dp, (1.0 + nq - fo[t]) * dm), contrib[t]);
+        for (int nu = 0; nu < NM; nu++)
+#pragma unroll
+          for (int mu = 0; mu < NM; mu++) {
+            uq[nu][mu] = a.uu32[(qidx * NM + nu) * NM + mu];
+          }
+#pragma unroll
+        for (int nu = 0; nu < NM; nu++) {
+          const double2 *r = reinterpret_cast<const double2 *>(a.occ_n + (qidx * NM + nu) * EPH_MAX_TEMPS);
+          const double2 r0 = r[0], r1 = r[1];
+          nqv[nu][0] = r0.x;
+          nqv[nu][1] = r0.y;
+          nqv[nu][2] = r1.x;
+          nqv[nu][3] = r1.y;
+        }
+        {
+          const double2 *r = reinterpret_cast<const double2 *>(a.occ_f + (pidx * NW + m) * EPH_MAX_TEMPS);
+          const double2 r0 = r[0], r1 = r[1];
+          fo[0] = r0.x;
+          fo[1] = r0.y;
+          fo[2] = r1.x;
+          fo[3] = r1.y;
+        }
+#pragma unroll
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = 0.0;
+        // every mode is evaluated and masked (about 5 of the 6 (nu, +-) terms
+        // of a vertex are kept, so branching would not save work)
+#pragma unroll
+        for (int nu = 0; nu < NM; nu++) {
+          const bool okp = (vp >> nu) & 1u, okm = (vm >> nu) & 1u;
+          T gr = 0, gi = 0;
+#pragma unroll
+          for (int mu = 0; mu < NM; mu++) cmac<T>(gr, gi, wr[mu], wi[mu], uq[nu][mu].x, uq[nu][mu].y);
+          const double g2 = fma((double)gr, (double)gr, (double)gi * (double)gi);
+          const double xp = es + omq[nu] - epm, xm = es - omq[nu] - epm;
+          const double ep = exp(-(xp * inv_eta) * (xp * inv_eta)), em = exp(-(xm * inv_eta) * (xm * inv_eta));
+          const double dp = okp ? ep * dnorm : 0.0, dm = okm ? em * dnorm : 0.0;
+#pragma unroll
+          for (int t = 0; t < EPH_MAX_TEMPS; t++)
+            contrib[t] = fma(g2, fma(nqv[nu][t] + fo[t], dp, (1.0 + nqv[nu][t] - fo[t]) * dm), contrib[t]);
         }
       }
 #pragma unroll
@@ -359,7 +310,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   auto vpop = [&](int n) __attribute__((always_inline)) {
     const int rem = vn - n;
     for (int b = 0; b < rem; b += 64) {
-      const uint32_t v = (b + lane < rem) ? sV[n + b + lane] : 0u;
+      const uint2 v = (b + lane < rem) ? sV[n + b + lane] : make_uint2(0u, 0u);
       __syncwarp();
       if (b + lane < rem) sV[b + lane] = v;
       __syncwarp();
@@ -375,6 +326,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
       const int line = sSlot[2 * zs_slot + 1], q2 = sSlot[2 * zs_slot];
       int q1 = p1 - sK1[ks];
       q1 += (q1 < 0) ? N : 0;
+      const int i1 = imod(q1 * lo1, N);
       const int64_t qidx = q1 + (int64_t)N * (q2 + (int64_t)N * a.q3_cur);
       const int64_t pidx = p1 + (int64_t)N * line;
       double om[NM], ep[NW];
@@ -411,8 +363,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
           const unsigned long long bits = __ballot(push);
           if (push)
             sV[vn + __popcll(bits & ((1ull << lane) - 1ull))] =
-                (uint32_t)p1 | ((uint32_t)s << 10) | ((uint32_t)m << 13) | ((uint32_t)zs_slot << 16) |
-                (vp << 18) | (vm << 24);
+                make_uint2((uint32_t)p1 | ((uint32_t)q1 << 10) | ((uint32_t)i1 << 20) | ((uint32_t)zs_slot << 30),
+                           (uint32_t)s | ((uint32_t)m << 3) | (vp << 6) | (vm << 12) | ((uint32_t)q2 << 18));
           vn += __popcll(bits);
         }
         hit = hit || hit_s;
@@ -483,23 +435,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
         bool stale = false;
         for (int b = 0; b < qn; b += 64)
           stale |= (b + lane < qn) && (int)(sQ[b + lane] >> 15) == zslot;
-        if constexpr (VQ) {
-          for (int b = 0; b < vn; b += 64)
-            stale |= (b + lane < vn) && (int)((sV[b + lane] >> 16) & 3u) == zslot;
-        }
+        for (int b = 0; b < vn; b += 64)
+          stale |= (b + lane < vn) && (int)(sV[b + lane].x >> 30) == zslot;
         if (__any(stale)) {
-          if constexpr (VQ) {
-            stage1(qn);
-            __syncwarp();
-            qn = 0;
-            vdrain(vn);
-            __syncwarp();
-            vn = 0;
-          } else {
-            drain(qn);
-            __syncwarp();
-            qn = 0;
-          }
+          stage1(qn);
+          __syncwarp();
+          qn = 0;
+          vdrain(vn);
+          __syncwarp();
+          vn = 0;
         }
       }
       {  // issue the loads of the next q-line's energies
@@ -568,38 +512,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
           if (any) sQ[qn + __popcll(bits & ((1ull << lane) - 1ull))] =
               (uint32_t)p1 | ((uint32_t)ks << 10) | ((uint32_t)zslot << 15);
           qn += __popcll(bits);
+          __syncwarp();
+          if (qn >= 64) {  // whole passes only, so the queue stays below 128
+            const int full = qn & ~63;
+            stage1(full);
+            __syncwarp();
+            pop(full);
+          }
         }
       }
       __syncwarp();
       // stage the next line's energies ([m][p1] in LDS); the scan of this
-      // line is done, and the drains below read energies from global memory
+      // line is done, and the drains read energies from global memory
 #pragma unroll
       for (int i = 0; i < LPL; i++) {
         const int e = lane + 64 * i;
         if (e < LN) sLine[(e % NW) * N + e / NW] = nxt[i];
       }
       __syncwarp();
-      if (qn >= 64) {  // evaluate whole passes only; the rest waits for later q-lines
-        const int full = qn & ~63;
-        if constexpr (VQ) {
-          stage1(full);
-          __syncwarp();
-          pop(full);
-        } else {
-          drain(full);
-          __syncwarp();
-          pop(full);
-        }
-      }
     }
   }
-  if constexpr (VQ) {
-    stage1(qn);
-    __syncwarp();
-    vdrain(vn);
-  } else {
-    drain(qn);
-  }
+  stage1(qn);
+  __syncwarp();
+  vdrain(vn);
 
   // ---- fixed-order reductions; q3 slabs add up in launch order ----
 #pragma unroll
@@ -638,15 +573,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   }
 }
 
-#ifndef EPH_WAVE_VQ
-#define EPH_WAVE_VQ 1
-#endif
 template <class T, int NW, int NM, int GW, int NB, int LPL>
 hipError_t launch_wave_l(const RatesArgs &a, hipStream_t st) {
   using LY = WaveLayout<T, NW, NM, GW, NB>;
   const size_t sh = LY::total(a.N);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL, EPH_WAVE_VQ != 0>;
+  auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
   const int64_t nblk = (a.ng + 3) / 4;
@@ -667,12 +599,14 @@ hipError_t launch_wave(const RatesArgs &a, hipStream_t st) {
 }  // namespace
 
 // Shapes served by the wave-autonomous kernel (cubic Rp box of edge 4 or 6).
-int rates_wave_group(int nw, int nm, RpBox box, int N) {
+int rates_wave_group(int nw, int nm, RpBox box, int N, int precision) {
   const bool cube = box.n[0] == box.n[1] && box.n[1] == box.n[2] && (box.n[0] == 4 || box.n[0] == 6);
   if (!cube || N * nw > 2048) return 0;
-  if (nm == 3 && (nw == 1 || nw == 2 || nw == 4)) return 2;
+  (void)precision;
+  const int g = 2;
+  if (nm == 3 && (nw == 1 || nw == 2 || nw == 4)) return g;
   if (nm == 3 && nw == 8) return 1;
-  if (nm == 6 && (nw == 1 || nw == 2)) return 2;
+  if (nm == 6 && (nw == 1 || nw == 2)) return g;
   if (nm == 6 && (nw == 4 || nw == 8)) return 1;
   return 0;
 }
@@ -680,17 +614,18 @@ int rates_wave_group(int nw, int nm, RpBox box, int N) {
 template <class T>
 static hipError_t wave_dispatch(const RatesArgs &a, hipStream_t st) {
   const int nb = a.box.n[0];
+  constexpr int G2 = 2;  // must match rates_wave_group
 #define EPH_W(NW_, NM_, GW_)                                         \
   if (a.nw == NW_ && a.nm == NM_) {                                  \
     if (nb == 4) return launch_wave<T, NW_, NM_, GW_, 4>(a, st);     \
     if (nb == 6) return launch_wave<T, NW_, NM_, GW_, 6>(a, st);     \
   }
-  EPH_W(1, 3, 2)
-  EPH_W(2, 3, 2)
-  EPH_W(4, 3, 2)
+  EPH_W(1, 3, G2)
+  EPH_W(2, 3, G2)
+  EPH_W(4, 3, G2)
   EPH_W(8, 3, 1)
-  EPH_W(1, 6, 2)
-  EPH_W(2, 6, 2)
+  EPH_W(1, 6, G2)
+  EPH_W(2, 6, G2)
   EPH_W(4, 6, 1)
   EPH_W(8, 6, 1)
 #undef EPH_W

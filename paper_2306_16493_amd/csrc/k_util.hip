@@ -61,13 +61,16 @@ __global__ void occupation_kernel(int64_t nq, int nw, int nm, const double *__re
                                   const double *__restrict__ om, double mu, int nt, Kts kts, double wcut,
                                   double *__restrict__ occ_f, double *__restrict__ occ_n) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // rows padded to EPH_MAX_TEMPS entries (zeros past nt) for vector loads
   if (i < nq * nw) {
     const double e = eps[i];
-    for (int t = 0; t < nt; t++) occ_f[i * nt + t] = 1.0 / (exp((e - mu) / kts.v[t]) + 1.0);
+    for (int t = 0; t < EPH_MAX_TEMPS; t++)
+      occ_f[i * EPH_MAX_TEMPS + t] = t < nt ? 1.0 / (exp((e - mu) / kts.v[t]) + 1.0) : 0.0;
   }
   if (i < nq * nm) {
     const double w = om[i];
-    for (int t = 0; t < nt; t++) occ_n[i * nt + t] = (w >= wcut && w > 0.0) ? 1.0 / expm1(w / kts.v[t]) : 0.0;
+    for (int t = 0; t < EPH_MAX_TEMPS; t++)
+      occ_n[i * EPH_MAX_TEMPS + t] = (t < nt && w >= wcut && w > 0.0) ? 1.0 / expm1(w / kts.v[t]) : 0.0;
   }
 }
 
