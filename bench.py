@@ -25,6 +25,25 @@ METRIC = "(k,q) el-ph pair evals/s + σ wall time at ≤1e-3 rel σ error vs FP6
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 157.3}   # FP64 / FP32 vector peaks of MI355X
 
 
+def measured_traffic(workload, precision):
+    """HBM bytes per rate-kernel launch from the committed counter summary
+    (profiles/rates_wave_traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by a copy kernel of known size), or None when that summary was
+    taken on another workload or on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "rates_wave_traffic.json")
+    src = os.path.join(ROOT, "paper_2306_16493_amd", "csrc", "k_rates_wave.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if t.get("source_sha256") != sha or t.get("workload") != workload or t.get("precision") != precision:
+        return None
+    return t["fetch_kib_per_launch"] * 1024 * t["fetch_scale"] + t["write_kib_per_launch"] * 1024 * t["write_scale"]
+
+
 def rate_kernel_flops(counts, ns, N, box, C, nm, nw):
     """FP64 flops the fused rate kernel executes (8 per complex MAC):
     Y stage 8*ns*N*nbox*C, Z stage 8*ns*N^2*n1*n2*C, and per vertex
@@ -65,10 +84,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="al_fcc_100")
+    ap.add_argument("--workload", default=None,
+                    help="default al_fcc_100 (bench line), si_fcc_150 (--report precision), al_fcc_200 (--report "
+                         "surrogate)")
     ap.add_argument("--grid", type=int, default=None)
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--cpu-sample", type=int, default=16, help="k points of the oracle sample (0 = skip)")
+    ap.add_argument("--report", choices=["precision", "surrogate"], default=None,
+                    help="instead of the bench line, measure the FP32/BF16x3 forms or the surrogate on "
+                         "their own workloads (one JSON line)")
+    ap.add_argument("--subset-frac", type=float, default=0.01, help="k-point fraction of --report precision")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -86,10 +111,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": 2 * x.numel() * 4, "launches": 5}), flush=True)
         return
+    if args.report == "precision":
+        from paper_2306_16493_amd import reports
+        wl = args.workload or "si_fcc_150"
+        print(json.dumps(reports.precision(wl, args.subset_frac, grid=args.grid)), flush=True)
+        return
+    if args.report == "surrogate":
+        from paper_2306_16493_amd import reports
+        wl = args.workload or "al_fcc_200"
+        print(json.dumps(reports.surrogate(wl, grid=args.grid, precision=args.precision)), flush=True)
+        return
     from synth import make_system, workload
     from paper_2306_16493_amd import Context
 
-    w = workload(args.workload, args.grid)
+    w = workload(args.workload or "al_fcc_100", args.grid)
     s = make_system(w.system)
     mu = s.mu_centroid
     lo, hi = mu + w.window[0], mu + w.window[1]
@@ -151,7 +186,7 @@ def main():
         "stages_ms": {"tables": st["tables_ms"], "prep": st["prep_ms"], "xform": float(np.mean(xform_ms)),
                       "rates": float(np.mean(rates_ms)), "call": st["call_ms"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(w.name, args.precision),
                      "kernel": "rates_wave_kernel", "flops_per_step": flops, "launches_per_step": n_launch,
                      "avg_launch_ms": np.mean(rates_ms) / n_launch, "flops_per_launch": flops / n_launch},
     }

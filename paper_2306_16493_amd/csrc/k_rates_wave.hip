@@ -19,13 +19,15 @@
 //   * phases use 32-bit indices advanced incrementally (no 64-bit modulo).
 // Per-state rates are accumulated per lane and reduced with a fixed
 // butterfly at the end, so results are bit-reproducible.
+#include <type_traits>
+
 #include "dev_util.h"
 #include "internal.h"
 
 namespace eph {
 namespace {
 
-template <class T, int NW, int NM, int GW, int NB>
+template <class T, int NW, int NM, int GW, int NB, class LT = double>
 struct WaveLayout {
   static constexpr int C = NW * NM;
   static constexpr int SMX = GW + NW;  // member states + shadow states
@@ -38,7 +40,7 @@ struct WaveLayout {
   __host__ __device__ static int qcap(int) { return 128; }  // drained in whole passes during the scan
   __host__ __device__ static size_t q_bytes(int N) { return align16(4 * (size_t)qcap(N)); }
   __host__ __device__ static size_t misc_bytes() { return align16(SMX * 8 + SMX * 4 * 4 + NZ * 8 + 64); }
-  __host__ __device__ static size_t line_bytes(int N) { return align16(8 * (size_t)N * NW); }
+  __host__ __device__ static size_t line_bytes(int N) { return align16(sizeof(LT) * (size_t)N * NW); }
   __host__ __device__ static size_t v_bytes() { return align16(8 * (size_t)VCAP); }
   __host__ __device__ static size_t per_wave(int N) {
     return z_bytes() + q_bytes(N) + misc_bytes() + line_bytes(N) + v_bytes();
@@ -54,7 +56,10 @@ template <class T, int NW, int NM, int GW, int NB, int LPL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OCC))) void rates_wave_kernel(
     RatesArgs a) {
   using C2 = typename V2<T>::t;
-  using LY = WaveLayout<T, NW, NM, GW, NB>;
+  // long lines keep a float copy of their energies for the prefilter, so
+  // that two workgroups still fit a CU's LDS
+  using LT = typename std::conditional<(LPL >= 16), float, double>::type;
+  using LY = WaveLayout<T, NW, NM, GW, NB, LT>;
   constexpr int C = NW * NM;
   constexpr int SMX = LY::SMX;
   constexpr int NZ = LY::NZ;
@@ -75,7 +80,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   int *sKcnt = sKfirst + SMX;                         // [SMX] states of each k-slot
   int *sK1 = sKcnt + SMX;                             // [SMX] k1 of each k-slot
   int *sSlot = sK1 + SMX;                             // [NZ][2] (q2, line) of each Z slot
-  double *sLine = reinterpret_cast<double *>(misc + LY::misc_bytes());  // [NW][N] current line energies
+  LT *sLine = reinterpret_cast<LT *>(misc + LY::misc_bytes());  // [NW][N] current line energies
   uint2 *sV = reinterpret_cast<uint2 *>(misc + LY::misc_bytes() + LY::line_bytes(N));  // vertex queue
 
   for (int t = threadIdx.x; t < N; t += 256) sTab[t] = mk<T>((T)a.tab[t].x, (T)a.tab[t].y);
@@ -100,7 +105,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   const int ST = S + SH;
   const bool cont = (s0 > 0) && (a.sk[s0 - 1] == kfirst);  // first k point counted by an earlier group
   const int k2 = (int)((kfirst / N) % N), k3 = (int)(kfirst / ((int64_t)N * N));
-  const double W = a.wmax + a.sw * a.eta;
+  // prefilter window (a float line copy is within 1e-4 eV of the FP64
+  // values for |eps| < 1000 eV; the exact sieve that follows uses FP64)
+  const double W = a.wmax + a.sw * a.eta + (sizeof(LT) == 4 ? 1e-4 : 0.0);
   const double cut = a.sw * a.eta;
   const double inv_eta = 1.0 / a.eta;
   const double dnorm = 1.0 / (1.7724538509055160273 * a.eta);
@@ -154,7 +161,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   {
     const int l3 = (k3 + a.q3_lo >= N) ? k3 + a.q3_lo - N : k3 + a.q3_lo;
     const double *l0 = a.eps + (size_t)(k2 + N * l3) * LN;
-    for (int e = lane; e < LN; e += 64) sLine[(e % NW) * N + e / NW] = l0[e];
+    for (int e = lane; e < LN; e += 64) sLine[(e % NW) * N + e / NW] = (LT)l0[e];
   }
 
   // One candidate = (k-slot, p1, Z slot): every state of that k point against
@@ -502,7 +509,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
           if (p1 < N) {
             double ev[NW];
 #pragma unroll
-            for (int m = 0; m < NW; m++) ev[m] = sLine[m * N + p1];
+            for (int m = 0; m < NW; m++) ev[m] = (double)sLine[m * N + p1];
 #pragma unroll
             for (int m = 0; m < NW; m++)
 #pragma unroll
@@ -527,7 +534,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 #pragma unroll
       for (int i = 0; i < LPL; i++) {
         const int e = lane + 64 * i;
-        if (e < LN) sLine[(e % NW) * N + e / NW] = nxt[i];
+        if (e < LN) sLine[(e % NW) * N + e / NW] = (LT)nxt[i];
       }
       __syncwarp();
     }
@@ -575,7 +582,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 
 template <class T, int NW, int NM, int GW, int NB, int LPL>
 hipError_t launch_wave_l(const RatesArgs &a, hipStream_t st) {
-  using LY = WaveLayout<T, NW, NM, GW, NB>;
+  using LY = WaveLayout<T, NW, NM, GW, NB, typename std::conditional<(LPL >= 16), float, double>::type>;
   const size_t sh = LY::total(a.N);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
   auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL>;

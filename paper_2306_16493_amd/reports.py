@@ -1,0 +1,158 @@
+"""Measurements of the two added forms on their own workloads (host-side
+orchestration only; every number comes from the HIP path through the C ABI).
+
+precision(): the FP32 and split-BF16x3 forms against the FP64 GPU path (which
+    the parity tests tie to the FP64 oracle) on a seeded subset of the k
+    points that carry states: per-state 1/tau and sigma errors, and the
+    speedup of each form's rates call over the FP64 one.
+surrogate(): the MLP-ensemble surrogate with plain fallback against the full
+    plain run on the same grid (assembled from disjoint k-subset runs):
+    sigma error and end-to-end speedup.
+
+Both print progress lines and return one dict (bench.py prints it as JSON).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def window(ctx, system, w, N):
+    """(mu, win_lo, win_hi) of a workload: relative to mu (metals, mu = band
+    centroid) or to the conduction-band minimum found on the grid (the
+    semiconductor, mu = CBM - 0.25 eV)."""
+    if w.window_relative_to == "mu":
+        mu = system.mu_centroid
+        return mu, mu + w.window[0], mu + w.window[1]
+    # lowest energy of band band_lo over the grid, from the library's own state list
+    p = ctx.params(N, 0.0, [300.0], w.eta, -1e6, 1e6, band_lo=w.band_lo, band_hi=w.band_lo)
+    _, _, e, _ = ctx.select_states(p)
+    cbm = float(e.min().item())
+    mu = cbm - 0.25 if w.mu_rule == "cbm-0.25" else system.mu_centroid
+    # 1e-7 eV below the CBM, so that the CBM state itself is inside the window
+    return mu, cbm + w.window[0] - 1e-7, cbm + w.window[1]
+
+
+def _timed_rates(ctx, params):
+    import torch
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, _ = ctx.scattering_rates(params)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.stage_times()
+    return res, wall, st
+
+
+def precision(workload_name="si_fcc_150", subset_frac=0.01, seed=1649307, grid=None):
+    from synth import make_system, workload
+    from .eph import Context
+    w = workload(workload_name, grid)
+    s = make_system(w.system)
+    ctx = Context(s, device=0)
+    N = w.grid
+    mu, lo, hi = window(ctx, s, w, N)
+    p_all = ctx.params(N, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi)
+    sk, _, _, _ = ctx.select_states(p_all)
+    kall = np.unique(sk.cpu().numpy())
+    rng = np.random.default_rng(seed)
+    nk = max(1, int(round(subset_frac * kall.size)))
+    ksub = np.sort(rng.choice(kall, size=nk, replace=False))
+    _log(f"[precision] {w.name} N={N}: {sk.shape[0]} states at {kall.size} k points; subset {nk} k points")
+    out = {"report": "precision", "workload": w.name, "grid": N, "n_states_total": int(sk.shape[0]),
+           "subset_k_points": int(nk), "subset_seed": seed, "forms": {}}
+    ref = None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        p = ctx.params(N, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision=prec, k_subset=ksub)
+        _timed_rates(ctx, p)  # warm-up (tables, lazy FP32/BF16 copies)
+        res, wall, st = _timed_rates(ctx, p)
+        sig = ctx.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, w.temps, N ** 3)
+        it = res.inv_tau.cpu().numpy()
+        entry = {"call_s": wall, "rates_ms": st["rates_ms"], "xform_ms": st["xform_ms"],
+                 "n_states": int(res.counts["n_states"]), "n_kq": int(res.counts["n_kq"]),
+                 "n_vertex": int(res.counts["n_vertex"]), "pairs_per_s": res.counts["n_kq"] / wall,
+                 "sigma_xx": [float(sig[t, 0, 0]) for t in range(sig.shape[0])]}
+        if prec == "fp64":
+            ref = (it, sig, wall, res.counts)
+        else:
+            it0, sig0, wall0, c0 = ref
+            pos = it0 > 0
+            rel = np.abs(it[pos] - it0[pos]) / it0[pos]
+            entry.update({"inv_tau_max_rel_err": float(rel.max()) if rel.size else 0.0,
+                          "inv_tau_median_rel_err": float(np.median(rel)) if rel.size else 0.0,
+                          "sigma_rel_err": float(np.max(np.abs(sig - sig0)) / np.max(np.abs(sig0))),
+                          "counts_equal": bool(res.counts["n_kq"] == c0["n_kq"]
+                                               and res.counts["n_terms"] == c0["n_terms"]),
+                          "speedup_vs_fp64": wall0 / wall})
+        out["forms"][prec] = entry
+        _log(f"[precision] {prec}: {wall:.2f} s, rates {st['rates_ms']:.0f} ms"
+             + (f", 1/tau max rel err {entry['inv_tau_max_rel_err']:.2e}, sigma rel err "
+                f"{entry['sigma_rel_err']:.2e}, speedup {entry['speedup_vs_fp64']:.2f}x" if prec != "fp64" else ""))
+    ctx.close()
+    return out
+
+
+def surrogate(workload_name="al_fcc_200", train_frac=0.02, chunks=8, threshold=0.01, members=5,
+              steps=3000, seed=1649307, grid=None, precision="fp64"):
+    """The surrogate run, then the plain kernel on every k point the
+    surrogate did not already compute with it (the full plain run is the
+    union of these disjoint k-subset runs: its 1/tau is the reference and its
+    time is the sum of their times)."""
+    import torch
+    from synth import make_system, workload
+    from .eph import Context, merge_rates
+    from . import surrogate as sg
+    w = workload(workload_name, grid)
+    s = make_system(w.system)
+    ctx = Context(s, device=0)
+    N = w.grid
+    mu, lo, hi = window(ctx, s, w, N)
+    temps = list(w.temps)
+    P = lambda ks: ctx.params(N, mu, temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision=precision, k_subset=ks)
+    # ---- surrogate with fallback ----
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = sg.run(ctx, N, mu, temps, w.eta, lo, hi, w.band_lo, w.band_hi, train_frac=train_frac, members=members,
+               steps=steps, threshold=threshold, seed=seed, precision=precision, log=_log)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t1
+    _log(f"[surrogate] surrogate run {t_sur:.1f} s: {r.times}")
+    sk, sn, se, sv = r.states
+    # ---- plain kernel on the remaining k points, in chunks ----
+    kall = np.unique(sk.cpu().numpy())
+    done = np.union1d(r.train_k, r.fallback_k)
+    rest = np.setdiff1d(kall, done)
+    ref = r.inv_tau.clone()  # plain values at the training and fallback k points
+    t_rest = 0.0
+    parts = [x for x in np.array_split(rest, chunks) if x.size]
+    for i, ks in enumerate(parts):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, _ = ctx.scattering_rates(P(ks))
+        torch.cuda.synchronize()
+        t_rest += time.perf_counter() - t0
+        merge_rates(ctx, sk, sn, ref, res.state_k, res.state_n, res.inv_tau)
+        _log(f"[surrogate] plain chunk {i + 1}/{len(parts)}: {res.counts['n_states']} states, {t_rest:.1f} s")
+    sig_ref = ctx.conductivity(se, sv, ref.reshape(-1), mu, temps, N ** 3)
+    t_plain = t_rest + r.times["train_rates_s"] + r.times["fallback_s"] + r.times["select_s"]
+    err = float(np.max(np.abs(r.sigma - sig_ref)) / np.max(np.abs(sig_ref)))
+    sig_net = ctx.conductivity(se, sv, r.raw_inv_tau.reshape(-1), mu, temps, N ** 3)
+    err_net = float(np.max(np.abs(sig_net - sig_ref)) / np.max(np.abs(sig_ref)))
+    out = {"report": "surrogate", "workload": w.name, "grid": N, "precision": precision,
+           "n_states": int(r.n_states), "k_points": int(kall.size), "train_k_points": int(r.n_train_k),
+           "train_states": int(r.n_train_states), "flagged_states": int(r.n_flagged),
+           "fallback_k_points": int(r.n_fallback_k), "threshold": threshold, "members": members,
+           "train_steps": steps, "member_loss": [float(x) for x in r.loss], "plain_s": t_plain,
+           "surrogate_s": t_sur, "speedup": t_plain / t_sur, "sigma_rel_err": err,
+           "sigma_rel_err_network_only": err_net, "stage_s": r.times,
+           "plain_time_note": "sum of the plain-kernel runs over disjoint k subsets covering every k point"}
+    _log(f"[surrogate] plain {t_plain:.1f} s, surrogate {t_sur:.1f} s (speedup {t_plain / t_sur:.2f}x), flagged "
+         f"{r.n_flagged}/{r.n_states}, sigma rel err {err:.2e} (network only {err_net:.2e})")
+    ctx.close()
+    return out

@@ -36,10 +36,13 @@ class SurrogateResult:
     times: dict = field(default_factory=dict)
     states: tuple = ()         # (k, n, e, v) device tensors
     raw_inv_tau: "object" = None  # network-only ensemble mean (before fallback)
+    train_k: "object" = None   # k points whose rates came from the plain kernel for training
+    fallback_k: "object" = None  # k points recomputed by the plain kernel
 
 
 def run(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_frac=0.02, members=5,
-        steps=2000, batch=256, lr=2e-3, threshold=0.01, seed=1649307, precision="fp64", log=None):
+        steps=2000, batch=256, lr=2e-3, threshold=0.01, seed=1649307, precision="fp64", log=None,
+        fallback_chunk=400000):
     import torch
     from .eph import Mlp, merge_rates
 
@@ -88,9 +91,13 @@ def run(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_
     merge_rates(ctx, sk, sn, inv_tau, tr.state_k, tr.state_n, tr.inv_tau)
     kflag = np.unique(sk[flag.bool()].cpu().numpy()) if nflag else np.zeros(0, np.int64)
     kflag = np.setdiff1d(kflag, ktrain)
-    if kflag.size:
-        fb, _ = ctx.scattering_rates(P(kflag))
+    # in chunks of at most fallback_chunk k points (bounded buffers, progress)
+    for c0 in range(0, kflag.size, fallback_chunk):
+        fb, _ = ctx.scattering_rates(P(kflag[c0:c0 + fallback_chunk]))
         merge_rates(ctx, sk, sn, inv_tau, fb.state_k, fb.state_n, fb.inv_tau)
+        torch.cuda.synchronize()
+        say(f"[surrogate] fallback {min(c0 + fallback_chunk, kflag.size)}/{kflag.size} k points, "
+            f"{time.perf_counter() - t4:.1f} s")
     torch.cuda.synchronize()
     times["fallback_s"] = time.perf_counter() - t4
     say(f"[surrogate] {nflag} states flagged, plain fallback at {kflag.size} k points")
@@ -98,4 +105,4 @@ def run(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_
     times["total_s"] = time.perf_counter() - t0
     mlp.close()
     return SurrogateResult(inv_tau, sig, ns, ntk, int(tr.state_k.shape[0]), nflag, int(kflag.size), loss, times,
-                           (sk, sn, se, sv), raw)
+                           (sk, sn, se, sv), raw, ktrain, kflag)

@@ -193,3 +193,32 @@ def test_al_fcc_100_full_size_sampled(torch_cuda):
     # the full-grid state count is a property of the whole run
     sk_all, _ = o.select_states(eps, w.band_lo, w.band_hi, lo, hi)
     assert len(sk_all) == ns
+
+
+def test_al_fcc_long_lines_k_subset(torch_cuda):
+    """Lines longer than 512 energies (N = 132, N*N_w = 528) take the kernel
+    variant with a float copy of the line for the prefilter; a seeded set of
+    k points is run on the GPU and compared with the oracle state by state."""
+    from paper_2306_16493_amd import Context
+    w = workload("al_fcc_100", 132)
+    s = make_system(w.system)
+    o = Oracle(s)
+    N = 132
+    mu = s.mu_centroid
+    lo, hi = mu + w.window[0], mu + w.window[1]
+    eps, evec, vel = o.electrons(N)
+    sk_all, _ = o.select_states(eps, w.band_lo, w.band_hi, lo, hi)
+    rng = np.random.default_rng(1649302 + 11)
+    kpick = np.sort(rng.choice(np.unique(sk_all), size=5, replace=False))
+    ctx = Context(s)
+    p, _ = params_for(ctx, w, s, N, k_subset=kpick)
+    log(f"[parity] al_fcc N={N} (long lines), {len(kpick)} k points")
+    g = gpu_run(ctx, p)
+    om, u, _ = o.phonons(N)
+    sk, sn = o.select_states(eps, w.band_lo, w.band_hi, lo, hi, k_subset=kpick)
+    r = o.rates(N, eps, evec, om, u, sk, sn, mu, w.temps, w.eta)
+    assert np.array_equal(g["state_k"], sk) and np.array_equal(g["state_n"], sn)
+    compare_rates(g, r["inv_tau"], eps, sk, sn)
+    c = g["counts"]
+    assert c["n_kq"] == r["n_kq"] and c["n_terms"] == int(r["n_terms"].sum())
+    ctx.close()
