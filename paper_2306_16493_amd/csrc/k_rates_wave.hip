@@ -9,14 +9,18 @@
 //     consecutive groups of the same k-line, so their table reads share L1;
 //   * Y_s(p1,p2; q3) lives in registers, one (state, p1, channel) pair per
 //     lane slot, so Z_s(p1; q2,q3) is a lane-local 1-D transform whose
-//     result goes to the wave's LDS slice;
+//     result goes to a ring of Z slots in the wave's LDS slice;
 //   * the final-state line p = k + q (contiguous in the energy table) is
-//     scanned 64 entries at a time; entries within max(hbar w) + sw*eta of a
-//     state's energy are compacted with ballots into an LDS queue, and the
-//     queue is drained in full passes of 64 lanes;
-//   * Fermi and Bose factors come from per-call grid tables, so a candidate
+//     prefiltered 64 entries at a time against the group's state energies
+//     (window max(hbar w) + sw*eta); passing (k-slot, p1) candidates are
+//     compacted with ballots into a candidate queue;
+//   * full passes of candidates are sieved exactly (FP64, every state and
+//     final band) and the (state, m, p1) pairs with a kept term go to a
+//     vertex queue; full passes of that queue evaluate one vertex per lane,
+//     so no lane idles through state, band or mode loops;
+//   * Fermi and Bose factors come from per-call grid tables, so a vertex
 //     pays one exp per kept term (the delta) and no other transcendental;
-//   * phases use 32-bit indices advanced incrementally (no 64-bit modulo).
+//   * phases use 32-bit indices and, in the vertex, a recurrence.
 // Per-state rates are accumulated per lane and reduced with a fixed
 // butterfly at the end, so results are bit-reproducible.
 #include <type_traits>
