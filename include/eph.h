@@ -194,6 +194,37 @@ int32_t eph_conductivity(eph_ctx *ctx, int64_t n_states, const double *energy_eV
                          int32_t n_temps, const double *temps_K, int64_t n_kpoints,
                          void *stream, double *sigma_S_per_m);
 
+/* Transport coefficients (Sec. II.C, the coefficients built from the same
+ * relaxation-time sums as sigma).  With energies in eV and
+ *   M_n,ab(T) = 2 e^2/(n_kpoints V) sum_s v_a v_b tau_s f(1-f)/(k_B T)
+ *               (eps_s - mu)^n,          n = 0, 1, 2,
+ * the outputs ([n_temps][3][3], HOST) are
+ *   sigma_S_per_m   = M_0,
+ *   seebeck_V_per_K = -M_0^-1 M_1 / T          (carriers of charge -e),
+ *   kappa_W_per_mK  = (M_2 - M_1 M_0^-1 M_1) / T (electronic thermal
+ *                     conductivity at zero electric current).
+ * Inputs as eph_conductivity (DEVICE state arrays, HOST temperatures); the
+ * three moments are fixed-order FP64 device reductions, the 3x3 algebra is
+ * done on the host.  A singular sigma gives non-finite S and kappa. */
+int32_t eph_transport(eph_ctx *ctx, int64_t n_states, const double *energy_eV, const double *vel_ms,
+                      const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K,
+                      int64_t n_kpoints, void *stream, double *sigma_S_per_m, double *seebeck_V_per_K,
+                      double *kappa_W_per_mK);
+
+/* Carrier density for mobilities (Sec. II.C, mobility = sigma / (n e)):
+ *   n(T) = 2/(N^3 V) sum_{all k of the N^3 grid} sum_{band_lo <= n <= band_hi} f(eps_nk)
+ * in m^-3 into n_per_m3 [n_temps] (HOST).  The band energies are computed on
+ * the full grid on the device (the electron half of the grid tables).
+ * EPH_E_INVALID for a bad grid (1..EPH_MAX_GRID), band range or
+ * temperature. */
+int32_t eph_carrier_density(eph_ctx *ctx, int32_t grid, int32_t band_lo, int32_t band_hi, double mu_eV,
+                            int32_t n_temps, const double *temps_K, void *stream, double *n_per_m3);
+
+/* Mobility tensor mu_ab = sigma_ab / (n e) in cm^2/(V s), from HOST arrays
+ * sigma_S_per_m [n_temps][3][3] and n_per_m3 [n_temps] into mobility_cm2
+ * [n_temps][3][3].  EPH_E_INVALID when a density is not positive. */
+int32_t eph_mobility(int32_t n_temps, const double *sigma_S_per_m, const double *n_per_m3, double *mobility_cm2);
+
 /* Stage timing.  With profiling on, eph_scattering_rates records HIP events
  * on its stream around its stages; eph_stage_times then returns their GPU
  * durations in milliseconds for the last call:

@@ -184,6 +184,19 @@ class Oracle:
                         _p(temps), _i64(nk_total), C.c_double(self.volume), _p(out))
         return out
 
+    def transport(self, energy, vel, inv_tau, mu, temps, nk_total):
+        """(sigma S/m, Seebeck V/K, electronic thermal conductivity W/(m K)),
+        each [nt][3][3], from the moments of the SERTA sum."""
+        energy = np.ascontiguousarray(energy, np.float64)
+        vel = np.ascontiguousarray(vel, np.float64)
+        inv_tau = np.ascontiguousarray(inv_tau, np.float64)
+        temps = np.ascontiguousarray(temps, np.float64)
+        ns, nt = energy.shape[0], temps.shape[0]
+        sig, see, kap = np.zeros((nt, 3, 3)), np.zeros((nt, 3, 3)), np.zeros((nt, 3, 3))
+        lib().orc_transport(_i64(ns), _p(energy), _p(vel), _p(inv_tau), C.c_double(mu), C.c_int32(nt), _p(temps),
+                            _i64(nk_total), C.c_double(self.volume), _p(sig), _p(see), _p(kap))
+        return sig, see, kap
+
     def carrier_density(self, eps, band_lo, band_hi, mu, temps):
         eps = np.ascontiguousarray(eps, np.float64)
         temps = np.ascontiguousarray(temps, np.float64)

@@ -22,6 +22,9 @@
  *               then the Rp sum at each q, then the band/mode rotations.
  *   rates       SERTA 1/tau (Sec. II.C), Gaussian delta, 1/N_q BZ average.
  *   sigma       sigma = 2 e^2/(N_k V) sum v v tau f(1-f)/(k_B T) (Sec. II.C).
+ *   transport   sigma, Seebeck and electronic thermal conductivity from the
+ *               (eps - mu)^n moments of the same sum (Sec. II.C);
+ *               carrier density for mobilities.
  * Loop order is the paper's CPU algorithm (Sec. III.A): outer loop over the
  * k points that carry states, inner loop over all q; OpenMP over k points.
  *
@@ -454,6 +457,70 @@ void orc_sigma(int64_t ns, const double *energy, const double *vel, const double
     }
     /* e^2 * [1/eV -> 1/J] = e^2/(e) = e */
     for (int e = 0; e < 9; e++) sigma[t * 9 + e] = 2.0 * ORC_E / ((double)nk_total * vol) * acc[e];
+  }
+}
+
+/* ---------------------------------------------------------------------
+ * Transport coefficients from the same SERTA sums (Sec. II.C, the
+ * coefficient definitions): with
+ *   M_n,ab(T) = 2e/(N_k V) sum_s v_a v_b tau f(1-f)/(k_B T) (eps_s - mu)^n
+ * (energies in eV, so M_0 = sigma in S/m),
+ *   sigma = M_0,
+ *   S     = -M_0^-1 M_1 / T                  (V/K, carriers of charge -e),
+ *   kappa = (M_2 - M_1 M_0^-1 M_1) / T       (W/(m K), zero electric current).
+ * Plain left-to-right sums; 3x3 inverse by cofactors.
+ * -------------------------------------------------------------------*/
+static void inv3(const double *a, double *r) {
+  const double c00 = a[4] * a[8] - a[5] * a[7], c01 = a[5] * a[6] - a[3] * a[8], c02 = a[3] * a[7] - a[4] * a[6];
+  const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+  r[0] = c00 / det;
+  r[3] = c01 / det;
+  r[6] = c02 / det;
+  r[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+  r[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+  r[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+  r[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+  r[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+  r[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+}
+static void mul3(const double *a, const double *b, double *r) {
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) r[i * 3 + j] = a[i * 3] * b[j] + a[i * 3 + 1] * b[3 + j] + a[i * 3 + 2] * b[6 + j];
+}
+
+void orc_transport(int64_t ns, const double *energy, const double *vel, const double *inv_tau, double mu,
+                   int32_t nt, const double *temps, int64_t nk_total, double volume_a3, double *sigma,
+                   double *seebeck, double *kappa) {
+  const double kb = orc_kb_evk();
+  const double vol = volume_a3 * 1e-30;
+  for (int t = 0; t < nt; t++) {
+    const double kt = kb * temps[t];
+    double m[3][9] = {{0}};
+    for (int64_t s = 0; s < ns; s++) {
+      const double it = inv_tau[t * ns + s];
+      if (it == 0.0) continue;
+      const double f = fermi(energy[s], mu, kt), de = energy[s] - mu;
+      const double w = f * (1.0 - f) / kt / it;
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+          const double x = vel[s * 3 + a] * vel[s * 3 + b] * w;
+          m[0][a * 3 + b] += x;
+          m[1][a * 3 + b] += x * de;
+          m[2][a * 3 + b] += x * de * de;
+        }
+    }
+    const double pref = 2.0 * ORC_E / ((double)nk_total * vol);
+    for (int n = 0; n < 3; n++)
+      for (int e = 0; e < 9; e++) m[n][e] *= pref;
+    double i0[9], s1[9], k1[9];
+    inv3(m[0], i0);
+    mul3(i0, m[1], s1);
+    mul3(m[1], s1, k1);
+    for (int e = 0; e < 9; e++) {
+      sigma[t * 9 + e] = m[0][e];
+      seebeck[t * 9 + e] = -s1[e] / temps[t];
+      kappa[t * 9 + e] = (m[2][e] - k1[e]) / temps[t];
+    }
   }
 }
 

@@ -4,5 +4,5 @@ The computation lives in the HIP library ``libeph.so`` behind the C ABI of
 ``include/eph.h``; ``eph`` is its Python binding.
 """
 from .eph import (  # noqa: F401
-    Context, EphError, RatesParams, Counts, lib, LIB_PATH, EXPORTS, PRECISIONS,
+    Context, EphError, RatesParams, Counts, lib, LIB_PATH, EXPORTS, PRECISIONS, mobility,
 )

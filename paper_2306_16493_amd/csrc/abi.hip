@@ -581,9 +581,14 @@ int32_t eph_stage_times(const eph_ctx *c, double *ms, int64_t *launches) {
   return EPH_OK;
 }
 
-int32_t eph_conductivity(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
-                         const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K,
-                         int64_t n_kpoints, void *stream, double *sigma_S_per_m) {
+}  // extern "C"
+
+namespace {
+// Moments 0..n_orders-1 of the SERTA sum on the device inputs, into host
+// out[order][EPH_MAX_TEMPS * 9] (S/m times eV^order).
+int32_t moments(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
+                const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K, int64_t n_kpoints,
+                void *stream, int n_orders, double (*out)[EPH_MAX_TEMPS * 9]) {
   if (!c) return EPH_E_INVALID;
   c->err.clear();
   if (n_states < 0) return fail(c, EPH_E_INVALID, "n_states < 0");
@@ -591,28 +596,137 @@ int32_t eph_conductivity(eph_ctx *c, int64_t n_states, const double *energy_eV, 
   for (int t = 0; t < n_temps; t++)
     if (!(temps_K[t] > 0.0) || !std::isfinite(temps_K[t])) return fail(c, EPH_E_INVALID, "temperatures must be > 0");
   if (n_kpoints < 1) return fail(c, EPH_E_INVALID, "n_kpoints must be >= 1");
-  if (!sigma_S_per_m) return fail(c, EPH_E_INVALID, "sigma output is NULL");
   if (n_states > 0 && (!energy_eV || !vel_ms || !inv_tau_s)) return fail(c, EPH_E_INVALID, "NULL input buffer");
   if (!std::isfinite(mu_eV)) return fail(c, EPH_E_INVALID, "mu must be finite");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Units U = units();
   const int nblk = 256;
-  // partials [nblk][36], then out [36], then kts [4]
-  EPH_HIP(c, c->sig_part.ensure(sizeof(double) * ((size_t)nblk * EPH_MAX_TEMPS * 9 + EPH_MAX_TEMPS * 9 + EPH_MAX_TEMPS)));
+  // partials [nblk][36], then out [3][36], then kts [4]
+  EPH_HIP(c, c->sig_part.ensure(sizeof(double) *
+                                ((size_t)nblk * EPH_MAX_TEMPS * 9 + 3 * EPH_MAX_TEMPS * 9 + EPH_MAX_TEMPS)));
   double *part = c->sig_part.as<double>();
   double *outd = part + (size_t)nblk * EPH_MAX_TEMPS * 9;
-  double *kts = outd + EPH_MAX_TEMPS * 9;
+  double *kts = outd + 3 * EPH_MAX_TEMPS * 9;
   double hk[EPH_MAX_TEMPS] = {1.0, 1.0, 1.0, 1.0};
   for (int t = 0; t < n_temps; t++) hk[t] = U.kb_evk * temps_K[t];
   EPH_HIP(c, hipMemcpyAsync(kts, hk, sizeof(hk), hipMemcpyHostToDevice, st));
   const double pref = 2.0 * kCharge / ((double)n_kpoints * c->volume * 1e-30);
-  EPH_HIP(c, launch_sigma(n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, kts, pref, part, nblk, outd, st));
-  double ho[EPH_MAX_TEMPS * 9];
+  for (int o = 0; o < n_orders; o++)
+    EPH_HIP(c, launch_sigma(n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, kts, pref, part, nblk,
+                            outd + o * EPH_MAX_TEMPS * 9, st, o));
+  EPH_HIP(c, hipMemcpyAsync(out, outd, sizeof(double) * n_orders * EPH_MAX_TEMPS * 9, hipMemcpyDeviceToHost, st));
+  EPH_HIP(c, hipStreamSynchronize(st));
+  return EPH_OK;
+}
+
+void inv3(const double *a, double *r) {
+  const double c00 = a[4] * a[8] - a[5] * a[7], c01 = a[5] * a[6] - a[3] * a[8], c02 = a[3] * a[7] - a[4] * a[6];
+  const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+  r[0] = c00 / det;
+  r[3] = c01 / det;
+  r[6] = c02 / det;
+  r[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+  r[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+  r[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+  r[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+  r[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+  r[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+}
+void mul3(const double *a, const double *b, double *r) {
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) r[i * 3 + j] = a[i * 3] * b[j] + a[i * 3 + 1] * b[3 + j] + a[i * 3 + 2] * b[6 + j];
+}
+}  // namespace
+
+extern "C" {
+
+int32_t eph_conductivity(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
+                         const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K,
+                         int64_t n_kpoints, void *stream, double *sigma_S_per_m) {
+  if (c && !sigma_S_per_m) return fail(c, EPH_E_INVALID, "sigma output is NULL");
+  double m[1][EPH_MAX_TEMPS * 9];
+  const int32_t r = moments(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints, stream, 1, m);
+  if (r != EPH_OK) return r;
+  for (int t = 0; t < n_temps; t++)
+    for (int q = 0; q < 9; q++) sigma_S_per_m[t * 9 + q] = m[0][t * 9 + q];
+  return EPH_OK;
+}
+
+int32_t eph_transport(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
+                      const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K,
+                      int64_t n_kpoints, void *stream, double *sigma_S_per_m, double *seebeck_V_per_K,
+                      double *kappa_W_per_mK) {
+  if (c && (!sigma_S_per_m || !seebeck_V_per_K || !kappa_W_per_mK))
+    return fail(c, EPH_E_INVALID, "NULL output");
+  double m[3][EPH_MAX_TEMPS * 9];
+  const int32_t r = moments(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints, stream, 3, m);
+  if (r != EPH_OK) return r;
+  for (int t = 0; t < n_temps; t++) {
+    const double *m0 = m[0] + t * 9, *m1 = m[1] + t * 9, *m2 = m[2] + t * 9;
+    double i0[9], s1[9], k1[9];
+    inv3(m0, i0);
+    mul3(i0, m1, s1);
+    mul3(m1, s1, k1);
+    for (int q = 0; q < 9; q++) {
+      sigma_S_per_m[t * 9 + q] = m0[q];
+      seebeck_V_per_K[t * 9 + q] = -s1[q] / temps_K[t];
+      kappa_W_per_mK[t * 9 + q] = (m2[q] - k1[q]) / temps_K[t];
+    }
+  }
+  return EPH_OK;
+}
+
+int32_t eph_carrier_density(eph_ctx *c, int32_t grid, int32_t band_lo, int32_t band_hi, double mu_eV,
+                            int32_t n_temps, const double *temps_K, void *stream, double *n_per_m3) {
+  if (!c) return EPH_E_INVALID;
+  c->err.clear();
+  if (grid < 1 || grid > EPH_MAX_GRID) return fail(c, EPH_E_INVALID, "grid must be 1..EPH_MAX_GRID");
+  if (band_lo < 0 || band_hi >= c->nw || band_lo > band_hi) return fail(c, EPH_E_INVALID, "bad band range");
+  if (n_temps < 1 || n_temps > EPH_MAX_TEMPS || !temps_K) return fail(c, EPH_E_INVALID, "bad temperatures");
+  for (int t = 0; t < n_temps; t++)
+    if (!(temps_K[t] > 0.0) || !std::isfinite(temps_K[t])) return fail(c, EPH_E_INVALID, "temperatures must be > 0");
+  if (!std::isfinite(mu_eV)) return fail(c, EPH_E_INVALID, "mu must be finite");
+  if (!n_per_m3) return fail(c, EPH_E_INVALID, "output is NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Units U = units();
+  const int N = grid, nw = c->nw;
+  const int64_t NQ = (int64_t)N * N * N;
+  // band energies on the full grid (the electron half of the grid tables)
+  EPH_HIP(c, c->tab.ensure(sizeof(double2) * N));
+  EPH_HIP(c, c->eps.ensure(sizeof(double) * NQ * nw));
+  EPH_HIP(c, c->evec.ensure(sizeof(double2) * NQ * nw * nw));
+  EPH_HIP(c, c->vel.ensure(sizeof(double) * NQ * nw * 3));
+  EPH_HIP(c, launch_phase_table(N, c->tab.as<double2>(), st));
+  EPH_HIP(c, launch_bloch_eig(0, nw, N, 0, NQ, c->nrh, c->rh.as<int>(), c->rh_w.as<double>(), c->rh_cart.as<double>(),
+                              c->ham.as<double2>(), c->tab.as<double2>(), nullptr, U.cph_ev, 0.0, U.vel_unit,
+                              c->eps.as<double>(), c->evec.as<double2>(), c->vel.as<double>(), nullptr, st));
+  const int nblk = 256;
+  EPH_HIP(c, c->sig_part.ensure(sizeof(double) * ((size_t)nblk * EPH_MAX_TEMPS + 2 * EPH_MAX_TEMPS)));
+  double *part = c->sig_part.as<double>();
+  double *outd = part + (size_t)nblk * EPH_MAX_TEMPS;
+  double *kts = outd + EPH_MAX_TEMPS;
+  double hk[EPH_MAX_TEMPS] = {1.0, 1.0, 1.0, 1.0};
+  for (int t = 0; t < n_temps; t++) hk[t] = U.kb_evk * temps_K[t];
+  EPH_HIP(c, hipMemcpyAsync(kts, hk, sizeof(hk), hipMemcpyHostToDevice, st));
+  const double pref = 2.0 / ((double)NQ * c->volume * 1e-30);
+  EPH_HIP(c, launch_density(NQ, nw, c->eps.as<double>(), band_lo, band_hi, mu_eV, n_temps, kts, pref, part, nblk,
+                            outd, st));
+  double ho[EPH_MAX_TEMPS];
   EPH_HIP(c, hipMemcpyAsync(ho, outd, sizeof(ho), hipMemcpyDeviceToHost, st));
   EPH_HIP(c, hipStreamSynchronize(st));
-  for (int t = 0; t < n_temps; t++)
-    for (int q = 0; q < 9; q++) sigma_S_per_m[t * 9 + q] = ho[t * 9 + q];
+  for (int t = 0; t < n_temps; t++) n_per_m3[t] = ho[t];
+  return EPH_OK;
+}
+
+int32_t eph_mobility(int32_t n_temps, const double *sigma_S_per_m, const double *n_per_m3, double *mobility_cm2) {
+  if (n_temps < 1 || n_temps > EPH_MAX_TEMPS || !sigma_S_per_m || !n_per_m3 || !mobility_cm2)
+    return EPH_E_INVALID;
+  for (int t = 0; t < n_temps; t++) {
+    if (!(n_per_m3[t] > 0.0)) return EPH_E_INVALID;
+    for (int q = 0; q < 9; q++) mobility_cm2[t * 9 + q] = sigma_S_per_m[t * 9 + q] / (n_per_m3[t] * kCharge) * 1e4;
+  }
   return EPH_OK;
 }
 

@@ -185,9 +185,13 @@ hipError_t launch_occupations(int64_t nq, int nw, int nm, const double *eps, con
 
 // sigma partial sums per block, then out[T*9 + ab] = pref * sum of partials
 // (partials: [nblk][EPH_MAX_TEMPS*9], out: [EPH_MAX_TEMPS*9], kts: device [nt]).
+// order n weights each state by (eps - mu)^n (n = 0: sigma)
 hipError_t launch_sigma(int64_t ns, const double *e, const double *v, const double *inv_tau, double mu,
                         int nt, const double *kts, double pref, double *partials, int nblk, double *out,
-                        hipStream_t st);
+                        hipStream_t st, int order = 0);
+// out[t] = pref * sum_{k, blo <= n <= bhi} f(eps_nk) (partials: [nblk][EPH_MAX_TEMPS])
+hipError_t launch_density(int64_t nk, int nw, const double *eps, int blo, int bhi, double mu, int nt,
+                          const double *kts, double pref, double *partials, int nblk, double *out, hipStream_t st);
 int rates_group_max(int nw, int nm);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_max_nonneg(int64_t n, const double *x, unsigned long long *out, hipStream_t st);

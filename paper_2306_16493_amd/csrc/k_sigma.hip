@@ -1,10 +1,13 @@
-// Conductivity reduction (Sec. II.C) and small element-wise helpers (gfx950).
+// Conductivity reduction and its energy moments (Sec. II.C), the carrier
+// density, and small element-wise helpers (gfx950).
 //
-// sigma_ab(T) = 2 e^2/(N_k V) sum_s v_a v_b tau_s f(1-f)/(k_B T): each block
-// reduces a contiguous chunk of states with Neumaier-compensated per-thread
-// sums and a fixed butterfly, writing [block][T][9] partials; a one-block
-// kernel then adds the partials in block order and applies the prefactor.
-// Results are bit-identical from run to run.
+// M_n,ab(T) = 2 e^2/(N_k V) sum_s v_a v_b tau_s f(1-f)/(k_B T) (eps_s - mu)^n
+// (n = 0 is sigma; eps in eV): each block reduces a contiguous chunk of
+// states with Neumaier-compensated per-thread sums and a fixed butterfly,
+// writing [block][T][9] partials; a one-block kernel then adds the partials
+// in block order and applies the prefactor.  The carrier density sums f over
+// the bands of the full grid the same way.  Results are bit-identical from
+// run to run.
 #include "internal.h"
 
 namespace eph {
@@ -23,7 +26,8 @@ __global__ __launch_bounds__(kSigThreads) void sigma_kernel(int64_t ns, const do
                                                              const double *__restrict__ v,
                                                              const double *__restrict__ inv_tau, double mu, int nt,
                                                              const double *__restrict__ kts,
-                                                             double *__restrict__ partials, int64_t chunk) {
+                                                             double *__restrict__ partials, int64_t chunk,
+                                                             int order) {
   __shared__ double red[kSigThreads / 64][EPH_MAX_TEMPS * 9];
   const int64_t b0 = blockIdx.x * chunk, b1 = min(ns, b0 + chunk);
   double s[EPH_MAX_TEMPS][9], c[EPH_MAX_TEMPS][9];
@@ -38,7 +42,8 @@ __global__ __launch_bounds__(kSigThreads) void sigma_kernel(int64_t ns, const do
       if (it == 0.0) continue;
       const double kt = kts[t];
       const double f = 1.0 / (exp((e[i] - mu) / kt) + 1.0);
-      const double w = f * (1.0 - f) / kt / it;
+      const double de = e[i] - mu;
+      const double w = f * (1.0 - f) / kt / it * (order == 0 ? 1.0 : order == 1 ? de : de * de);
       for (int q = 0; q < 9; q++) neumaier(s[t][q], c[t][q], vv[q] * w);
     }
   }
@@ -66,6 +71,46 @@ __global__ void sigma_final_kernel(int nblk, const double *__restrict__ partials
   out[q] = pref * (s + c);
 }
 
+// sum over k of f(eps_nk) for band_lo <= n <= band_hi, per temperature
+__global__ __launch_bounds__(kSigThreads) void density_kernel(int64_t nk, int nw, const double *__restrict__ eps,
+                                                               int blo, int bhi, double mu, int nt,
+                                                               const double *__restrict__ kts,
+                                                               double *__restrict__ partials, int64_t chunk) {
+  __shared__ double red[kSigThreads / 64][EPH_MAX_TEMPS];
+  const int64_t b0 = blockIdx.x * chunk, b1 = min(nk, b0 + chunk);
+  double s[EPH_MAX_TEMPS], c[EPH_MAX_TEMPS];
+  for (int t = 0; t < EPH_MAX_TEMPS; t++) s[t] = c[t] = 0.0;
+  for (int64_t k = b0 + threadIdx.x; k < b1; k += kSigThreads)
+    for (int n = blo; n <= bhi; n++) {
+      const double e = eps[k * nw + n];
+      for (int t = 0; t < EPH_MAX_TEMPS; t++) {
+        if (t >= nt) break;
+        neumaier(s[t], c[t], 1.0 / (exp((e - mu) / kts[t]) + 1.0));
+      }
+    }
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  for (int t = 0; t < EPH_MAX_TEMPS; t++) {
+    double x = s[t] + c[t];
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    if (lane == 0) red[wave][t] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < EPH_MAX_TEMPS) {
+    double x = 0.0;
+    for (int w = 0; w < kSigThreads / 64; w++) x += red[w][threadIdx.x];
+    partials[blockIdx.x * EPH_MAX_TEMPS + threadIdx.x] = x;
+  }
+}
+
+__global__ void density_final_kernel(int nblk, const double *__restrict__ partials, double pref,
+                                     double *__restrict__ out) {
+  const int t = threadIdx.x;
+  if (t >= EPH_MAX_TEMPS) return;
+  double s = 0.0, c = 0.0;
+  for (int b = 0; b < nblk; b++) neumaier(s, c, partials[b * EPH_MAX_TEMPS + t]);
+  out[t] = pref * (s + c);
+}
+
 __global__ void to_f32_kernel(int64_t n, const double2 *__restrict__ in, float2 *__restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
@@ -75,12 +120,22 @@ __global__ void to_f32_kernel(int64_t n, const double2 *__restrict__ in, float2 
 
 hipError_t launch_sigma(int64_t ns, const double *e, const double *v, const double *inv_tau, double mu, int nt,
                         const double *kts, double pref, double *partials, int nblk, double *out,
-                        hipStream_t st) {
+                        hipStream_t st, int order) {
   int64_t chunk = (ns + nblk - 1) / nblk;
   if (chunk < 1) chunk = 1;
   hipLaunchKernelGGL(sigma_kernel, dim3(nblk), dim3(kSigThreads), 0, st, ns, e, v, inv_tau, mu, nt, kts, partials,
-                     chunk);
+                     chunk, order);
   hipLaunchKernelGGL(sigma_final_kernel, dim3(1), dim3(64), 0, st, nblk, partials, pref, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_density(int64_t nk, int nw, const double *eps, int blo, int bhi, double mu, int nt,
+                          const double *kts, double pref, double *partials, int nblk, double *out, hipStream_t st) {
+  int64_t chunk = (nk + nblk - 1) / nblk;
+  if (chunk < 1) chunk = 1;
+  hipLaunchKernelGGL(density_kernel, dim3(nblk), dim3(kSigThreads), 0, st, nk, nw, eps, blo, bhi, mu, nt, kts,
+                     partials, chunk);
+  hipLaunchKernelGGL(density_final_kernel, dim3(1), dim3(64), 0, st, nblk, partials, pref, out);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ MAX_TEMPS = 4
 
 # every symbol declared in include/eph.h
 EXPORTS = ("eph_load_wannier", "eph_free", "eph_last_error", "eph_scattering_rates", "eph_select_states",
-           "eph_conductivity",
+           "eph_conductivity", "eph_transport", "eph_carrier_density", "eph_mobility",
            "eph_set_profiling", "eph_stage_times", "eph_mlp_create", "eph_mlp_free", "eph_mlp_params",
            "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient", "eph_mlp_predict", "eph_mlp_blend",
            "eph_merge_rates")
@@ -101,8 +101,12 @@ def lib():
         L.eph_mlp_predict.argtypes = [vp, i64, vp, vp, vp]
         L.eph_mlp_blend.argtypes = [vp, i64, vp, f64, vp, vp, C.POINTER(i64), vp]
         L.eph_merge_rates.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, i32, vp, vp]
+        L.eph_transport.argtypes = [vp, i64, vp, vp, vp, f64, i32, vp, i64, vp, vp, vp, vp]
+        L.eph_carrier_density.argtypes = [vp, i32, i32, i32, f64, i32, vp, vp, vp]
+        L.eph_mobility.argtypes = [i32, vp, vp, vp]
         for f in ("eph_mlp_create", "eph_mlp_params", "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient",
-                  "eph_mlp_predict", "eph_mlp_blend", "eph_merge_rates"):
+                  "eph_mlp_predict", "eph_mlp_blend", "eph_merge_rates", "eph_transport", "eph_carrier_density",
+                  "eph_mobility"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -268,6 +272,50 @@ class Context:
                                     int(n_kpoints), C.c_void_p(stream) if stream else None, _ptr(out))
         self._check(st)
         return out
+
+
+def _conductivity_args(energy, vel, inv_tau):
+    return energy.contiguous(), vel.contiguous(), inv_tau.contiguous()
+
+
+class _Transport:
+    """Transport coefficients of a Context (mixed into Context below)."""
+
+    def transport(self, energy, vel, inv_tau, mu, temps, n_kpoints, stream=None):
+        """(sigma S/m, Seebeck V/K, electronic kappa W/(m K)), each [nt][3][3]."""
+        temps = np.ascontiguousarray(np.atleast_1d(temps), np.float64)
+        nt = temps.shape[0]
+        sig, see, kap = np.zeros((nt, 3, 3)), np.zeros((nt, 3, 3)), np.zeros((nt, 3, 3))
+        e, v, it = _conductivity_args(energy, vel, inv_tau)
+        st = lib().eph_transport(self._h, int(energy.shape[0]), _dptr(e), _dptr(v), _dptr(it), float(mu), nt,
+                                 _ptr(temps), int(n_kpoints), C.c_void_p(stream) if stream else None, _ptr(sig),
+                                 _ptr(see), _ptr(kap))
+        self._check(st)
+        return sig, see, kap
+
+    def carrier_density(self, grid, band_lo, band_hi, mu, temps, stream=None):
+        """n(T) in m^-3 over bands band_lo..band_hi of the full grid."""
+        temps = np.ascontiguousarray(np.atleast_1d(temps), np.float64)
+        out = np.zeros(temps.shape[0])
+        st = lib().eph_carrier_density(self._h, int(grid), int(band_lo), int(band_hi), float(mu), temps.shape[0],
+                                       _ptr(temps), C.c_void_p(stream) if stream else None, _ptr(out))
+        self._check(st)
+        return out
+
+
+def mobility(sigma, n_per_m3):
+    """sigma [nt][3][3] (S/m) and n [nt] (m^-3) -> mobility [nt][3][3] in cm^2/(V s)."""
+    sigma = np.ascontiguousarray(sigma, np.float64)
+    n = np.ascontiguousarray(np.atleast_1d(n_per_m3), np.float64)
+    out = np.zeros_like(sigma)
+    st = lib().eph_mobility(n.shape[0], _ptr(sigma), _ptr(n), _ptr(out))
+    if st != 0:
+        raise EphError(st, "eph_mobility: densities must be positive")
+    return out
+
+
+for _name in ("transport", "carrier_density"):
+    setattr(Context, _name, getattr(_Transport, _name))
 
 
 class Mlp:

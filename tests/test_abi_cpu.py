@@ -125,3 +125,16 @@ def test_valid_model_without_gpu_reports_device_error():
     m, keep = _model(make_system("toy_sc"))
     st, msg = _load(m)
     assert st in (eph.EPH_E_DEVICE, eph.EPH_OK)
+
+
+def test_mobility_host_arithmetic():
+    """eph_mobility is host arithmetic: mu = sigma / (n e), in cm^2/(V s)."""
+    from paper_2306_16493_amd import mobility
+    from paper_2306_16493_amd.eph import EphError
+    sig = np.arange(18, dtype=np.float64).reshape(2, 3, 3) * 1e5
+    n = np.array([1e24, 2e25])
+    mu = mobility(sig, n)
+    ref = sig / (n[:, None, None] * 1.602176634e-19) * 1e4
+    assert np.allclose(mu, ref, rtol=1e-15, atol=0)
+    with pytest.raises(EphError):
+        mobility(sig, np.array([1e24, 0.0]))

@@ -441,3 +441,50 @@ def test_counts_vs_numpy_sieve():
             anyk |= ok.any(axis=(1, 2, 3))
         nkq += anyk.sum()
     assert nkq == r["n_kq"]
+
+
+# ---------------------------------------------------------------- transport coefficients
+def test_transport_sigma_moment_equals_sigma():
+    """The zeroth moment is sigma itself (same sum, same order)."""
+    o = Oracle(nn_band(0.0, -0.4))
+    eps, _, vel = o.electrons(6)
+    rng = np.random.default_rng(5)
+    inv = rng.uniform(1e13, 3e13, (2, 6 ** 3))
+    sig, see, kap = o.transport(eps[:, 0], vel[:, 0], inv, 0.1, [300.0, 500.0], 6 ** 3)
+    ref = o.sigma(eps[:, 0], vel[:, 0], inv, 0.1, [300.0, 500.0], 6 ** 3)
+    assert np.allclose(sig, ref, rtol=1e-13, atol=0)
+
+
+def test_seebeck_vanishes_for_particle_hole_symmetric_band():
+    """NN simple-cubic band with mu at its centre and constant tau: states at
+    eps0 + x and eps0 - x come in pairs (k -> k + (1/2,1/2,1/2)) with equal
+    v v f(1-f), so the first moment and the Seebeck coefficient vanish; off
+    centre it does not: below the centre the Fermi surface is electron-like
+    (sigma(E) grows with E, so S < 0 by Mott's formula for charge -e
+    carriers), above it hole-like (S > 0), with equal magnitudes."""
+    o = Oracle(nn_band(0.0, -0.1))
+    N = 16
+    eps, _, vel = o.electrons(N)
+    inv = np.full((1, N ** 3), 1e13)
+    _, see0, _ = o.transport(eps[:, 0], vel[:, 0], inv, 0.0, [600.0], N ** 3)
+    _, see_lo, _ = o.transport(eps[:, 0], vel[:, 0], inv, -0.3, [600.0], N ** 3)
+    _, see_hi, _ = o.transport(eps[:, 0], vel[:, 0], inv, 0.3, [600.0], N ** 3)
+    scale = abs(see_lo[0, 0, 0])
+    assert scale > 1e-6
+    assert np.max(np.abs(see0)) < 1e-10 * scale
+    assert see_lo[0, 0, 0] < 0 < see_hi[0, 0, 0]
+    assert see_hi[0, 0, 0] == pytest.approx(-see_lo[0, 0, 0], rel=1e-10)
+
+
+def test_wiedemann_franz_degenerate_limit():
+    """Constant tau, Fermi level inside a wide band, k_B T << band width:
+    the Sommerfeld expansion gives kappa / (sigma T) = (pi^2/3)(k_B/e)^2,
+    with corrections of relative order (k_B T / W)^2 (here ~1e-3)."""
+    o = Oracle(nn_band(0.0, -1.0))
+    N = 48
+    eps, _, vel = o.electrons(N)
+    inv = np.full((1, N ** 3), 1e13)
+    T = 1500.0
+    sig, _, kap = o.transport(eps[:, 0], vel[:, 0], inv, -1.5, [T], N ** 3)
+    lorenz = kap[0, 0, 0] / (sig[0, 0, 0] * T)
+    assert lorenz == pytest.approx(math.pi ** 2 / 3 * (sc.k / sc.e) ** 2, rel=0.03)
