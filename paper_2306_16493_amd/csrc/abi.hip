@@ -482,6 +482,12 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     a.n_kq = ctr + 2;
     a.n_vertex = ctr + 6;
     a.evec32 = fp32 ? c->evec32.as<float2>() : nullptr;
+    a.eps32 = nullptr;
+    if (gwave > 0 && N * nw > 512) {  // the wave kernel prefilters long lines from a float copy
+      EPH_HIP(c, c->eps32.ensure(sizeof(float) * NQ * nw));
+      EPH_HIP(c, launch_real_to_f32(NQ * nw, c->eps.as<double>(), c->eps32.as<float>(), st));
+      a.eps32 = c->eps32.as<float>();
+    }
     a.uu32 = fp32 ? c->uu32.as<float2>() : nullptr;
     a.occ_f = c->occ.as<double>();
     a.occ_n = c->occ.as<double>() + (size_t)NQ * nw * EPH_MAX_TEMPS;

@@ -68,6 +68,7 @@ struct eph_ctx {
   eph::DevBuf tab;                      // e^{2 pi i m/N}, [N] double2
   eph::DevBuf eps, evec, vel, om, uu;   // grid tables
   eph::DevBuf evec32, uu32;             // FP32 copies for reduced forms
+  eph::DevBuf eps32;                    // float band energies (prefilter of long lines)
   eph::DevBuf cnt, offs, scan_tmp, subset;
   eph::DevBuf grp_start, grp_tmp;
   eph::DevBuf line_e, line_key;         // energy-sorted p-lines
@@ -128,6 +129,7 @@ hipError_t launch_xform64(int64_t ns, const int32_t *sk, const int32_t *sn, int 
 hipError_t launch_xform32(int64_t ns, const int32_t *sk, const int32_t *sn, int N, int nw, int nre,
                           const int *re, int ncol, const float2 *wt, const double2 *evec,
                           const double2 *tab, float2 *X, hipStream_t st);
+hipError_t launch_real_to_f32(int64_t n, const double *in, float *out, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double2 *in, float2 *out, hipStream_t st);
 // bf16 hi/lo split of the g operand in real form (2 * bf16_w_elems bf16 values)
 size_t bf16_w_elems(int nre, int nw, int ncol);
@@ -151,6 +153,7 @@ struct RatesArgs {
   const double2 *evec;             // [N^3][nw][nw]
   const double2 *uu;               // [N^3][nm][nm]
   const float2 *evec32, *uu32;
+  const float *eps32;              // float copy of eps (prefilter of lines longer than 512 energies)
   const double *line_e;
   const uint16_t *line_key;
   const double2 *tab;

@@ -161,10 +161,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 
   // final-state line energies: the next q-line's are loaded into registers
   // while the current one (in LDS, [m][p1]) is scanned
-  double nxt[LPL];
+  LT nxt[LPL];
+  const LT *eline;  // energy table the prefilter reads (FP64, or its float copy for long lines)
+  if constexpr (sizeof(LT) == 4) eline = a.eps32;
+  else eline = a.eps;
   {
     const int l3 = (k3 + a.q3_lo >= N) ? k3 + a.q3_lo - N : k3 + a.q3_lo;
-    const double *l0 = a.eps + (size_t)(k2 + N * l3) * LN;
+    const LT *l0 = eline + (size_t)(k2 + N * l3) * LN;
     for (int e = lane; e < LN; e += 64) sLine[(e % NW) * N + e / NW] = (LT)l0[e];
   }
 
@@ -465,11 +468,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
         }
         const int n2l = (k2 + nq2 >= N) ? k2 + nq2 - N : k2 + nq2;
         const int n3l = (k3 + nq3 >= N) ? k3 + nq3 - N : k3 + nq3;
-        const double *ln = a.eps + (size_t)(n2l + N * n3l) * LN;
+        const LT *ln = eline + (size_t)(n2l + N * n3l) * LN;
 #pragma unroll
         for (int i = 0; i < LPL; i++) {
           const int e = lane + 64 * i;
-          nxt[i] = (e < LN) ? ln[e] : 0.0;
+          nxt[i] = (e < LN) ? ln[e] : (LT)0;
         }
       }
       // ---- Z_s(p1; q2, q3) -> LDS slot ----

@@ -111,6 +111,11 @@ __global__ void density_final_kernel(int nblk, const double *__restrict__ partia
   out[t] = pref * (s + c);
 }
 
+__global__ void real_to_f32_kernel(int64_t n, const double *__restrict__ in, float *__restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
 __global__ void to_f32_kernel(int64_t n, const double2 *__restrict__ in, float2 *__restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
@@ -136,6 +141,12 @@ hipError_t launch_density(int64_t nk, int nw, const double *eps, int blo, int bh
   hipLaunchKernelGGL(density_kernel, dim3(nblk), dim3(kSigThreads), 0, st, nk, nw, eps, blo, bhi, mu, nt, kts,
                      partials, chunk);
   hipLaunchKernelGGL(density_final_kernel, dim3(1), dim3(64), 0, st, nblk, partials, pref, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_to_f32(int64_t n, const double *in, float *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(real_to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, in, out);
   return hipGetLastError();
 }
 
