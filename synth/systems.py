@@ -184,8 +184,13 @@ def make_system(name: str, seed: Optional[int] = None, real_g: bool = False) -> 
               6^3 x 6^3
     'si_fcc'  Si-like fcc 2-atom semiconductor, 8 orbitals (onsite -3 eV on
               1-4, +3 eV on 5-8), H on 8^3, D on 6^3, g on 8^3 x 6^3
+    'mini_w1', 'mini_w8', 'mini_w2a2', 'mini_w4a2'
+              small models covering the other (orbitals, modes) shapes:
+              1 or 8 orbitals with 1 atom, 2 or 4 orbitals with 2 atoms;
+              every block 4^3
     """
-    defaults = {"toy_sc": 1649301, "al_fcc": 1649302, "si_fcc": 1649303}
+    defaults = {"toy_sc": 1649301, "al_fcc": 1649302, "si_fcc": 1649303,
+                "mini_w1": 1649311, "mini_w2a2": 1649312, "mini_w8": 1649313, "mini_w4a2": 1649314}
     if seed is None:
         seed = defaults[name]
     rng = np.random.default_rng(seed)
@@ -202,6 +207,20 @@ def make_system(name: str, seed: Optional[int] = None, real_g: bool = False) -> 
         mass, nw = np.array([28.0855, 28.0855]), 8
         nh, nd, ne, npv = 8, 6, 8, 6
         onsite = np.array([-3.0] * 4 + [3.0] * 4)
+    elif name in ("mini_w1", "mini_w8"):
+        # shape-coverage models: 1 atom with 1 or 8 orbitals, 4^3 blocks
+        nw = 1 if name == "mini_w1" else 8
+        lat = _sc(3.0) if nw == 1 else _fcc(4.0)
+        tau, mass = np.zeros((1, 3)), np.array([26.98])
+        nh, nd, ne, npv, onsite = 4, 4, 4, 4, None
+    elif name in ("mini_w2a2", "mini_w4a2"):
+        # shape-coverage models: 2 atoms (6 modes) with 2 or 4 orbitals
+        a = 3.5
+        lat = _sc(a)
+        tau = np.array([[0.0, 0.0, 0.0], [0.5 * a, 0.5 * a, 0.5 * a]])
+        mass = np.array([26.98, 40.0])
+        nw = 2 if name == "mini_w2a2" else 4
+        nh, nd, ne, npv, onsite = 4, 4, 4, 4, None
     else:
         raise KeyError(name)
     rh, rh_w = ws_block(nh)

@@ -165,7 +165,7 @@ def test_velocity_finite_difference(name):
 
 
 # ---------------------------------------------------------------- P3
-@pytest.mark.parametrize("name", ["toy_sc", "al_fcc", "si_fcc"])
+@pytest.mark.parametrize("name", ["toy_sc", "al_fcc", "si_fcc", "mini_w2a2", "mini_w4a2"])
 def test_acoustic_sum_rule_and_psd(name):
     """D(q) from the spring construction: three zero modes at Gamma (acoustic
     sum rule), positive semidefinite on the whole grid, max w <= 40 meV."""
