@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--report", choices=["precision", "surrogate"], default=None,
                     help="instead of the bench line, measure the FP32/BF16x3 forms or the surrogate on "
                          "their own workloads (one JSON line)")
+    ap.add_argument("--fp32-form", type=int, default=1,
+                    help="with --precision fp64, also time the FP32 form (extra 'fp32_form' key; 0 = skip)")
     ap.add_argument("--subset-frac", type=float, default=0.01, help="k-point fraction of --report precision")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
@@ -145,10 +147,13 @@ def main():
         step()
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    rates_ms, xform_ms, launches = [], [], 0
+    rates_ms, xform_ms, launches, step_s = [], [], 0, []
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ts = time.perf_counter()
         res, sig = step()
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
         st = ctx.stage_times()
         rates_ms.append(st["rates_ms"])
         xform_ms.append(st["xform_ms"])
@@ -182,6 +187,7 @@ def main():
                    "n_kq": counts["n_kq"], "n_nkq": counts["n_nkq"], "n_terms": counts["n_terms"],
                    "n_vertex": counts["n_vertex"]},
         "sigma_wall_s": t,
+        "ms_per_step_median": float(np.median(step_s)) * 1e3,
         "sigma_S_per_m_xx": [float(sig[i, 0, 0]) for i in range(sig.shape[0])],
         "stages_ms": {"tables": st["tables_ms"], "prep": st["prep_ms"], "xform": float(np.mean(xform_ms)),
                       "rates": float(np.mean(rates_ms)), "call": st["call_ms"]},
@@ -190,6 +196,24 @@ def main():
                      "kernel": "rates_wave_kernel", "flops_per_step": flops, "launches_per_step": n_launch,
                      "avg_launch_ms": np.mean(rates_ms) / n_launch, "flops_per_launch": flops / n_launch},
     }
+    if args.precision == "fp64" and args.fp32_form:
+        # the FP32 form on the same workload (same timed protocol), with its
+        # sigma error against this FP64 run: the metric admits forms within
+        # 1e-3 relative sigma error; the headline value above stays FP64
+        p32 = ctx.params(w.grid, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision="fp32")
+        bufs = None
+        res32, bufs = ctx.scattering_rates(p32, capacity=ns, buffers=bufs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            res32, bufs = ctx.scattering_rates(p32, capacity=ns, buffers=bufs)
+            sig32 = ctx.conductivity(res32.energy, res32.vel, res32.inv_tau.reshape(-1), mu, w.temps, w.grid ** 3)
+        torch.cuda.synchronize()
+        t32 = (time.perf_counter() - t1) / args.steps
+        out["fp32_form"] = {"ms_per_step": t32 * 1e3, "value": res32.counts["n_kq"] / t32,
+                            "speedup_vs_fp64": t / t32,
+                            "sigma_rel_err_vs_fp64": float(np.max(np.abs(sig32 - sig)) / np.max(np.abs(sig)))}
+        print(f"[bench] fp32 form: {t32 * 1e3:.1f} ms per step", file=sys.stderr, flush=True)
     if args.cpu_sample > 0:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, w, mu, lo, hi, res.state_k.cpu().numpy(), args.cpu_sample)
