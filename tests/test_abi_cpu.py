@@ -113,6 +113,17 @@ def test_null_arguments():
     L.eph_free(None)  # NULL-safe
     assert L.eph_scattering_rates(None, None, 0, None, None, None, None, None, None) == eph.EPH_E_INVALID
     assert L.eph_conductivity(None, 0, None, None, None, 0.0, 1, None, 1, None, None) == eph.EPH_E_INVALID
+    assert L.eph_transport(None, 0, None, None, None, 0.0, 1, None, 1, None, None, None, None) == eph.EPH_E_INVALID
+    t = np.array([300.0])
+    out = np.zeros(1)
+    assert L.eph_carrier_density(None, 4, 0, 0, 0.0, 1, t.ctypes.data_as(C.c_void_p), None,
+                                 out.ctypes.data_as(C.c_void_p)) == eph.EPH_E_INVALID
+    assert L.eph_mobility(0, None, None, None) == eph.EPH_E_INVALID
+    assert L.eph_mlp_create(None, 5, 1, 0, None) == eph.EPH_E_INVALID
+    assert L.eph_mlp_params(None, None, None, 0) == eph.EPH_E_INVALID
+    assert L.eph_mlp_train(None, 0, None, None, 0, 0, 0.0, None, None) == eph.EPH_E_INVALID
+    assert L.eph_mlp_predict(None, 0, None, None, None) == eph.EPH_E_INVALID
+    assert L.eph_mlp_blend(None, 0, None, 0.0, None, None, None, None) == eph.EPH_E_INVALID
 
 
 def test_valid_model_without_gpu_reports_device_error():
