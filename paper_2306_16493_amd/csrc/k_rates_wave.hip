@@ -161,7 +161,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 
   // final-state line energies: the next q-line's are loaded into registers
   // while the current one (in LDS, [m][p1]) is scanned
-  LT nxt[LPL];
+  // lines up to 1024 energies are prefetched into registers while a line is
+  // worked on; longer ones are copied at the staging point (their registers
+  // would push the kernel into spilling)
+  constexpr bool PF = LPL <= 16;
+  constexpr int LPR = PF ? LPL : 1;
+  LT nxt[LPR];
   const LT *eline;  // energy table the prefilter reads (FP64, or its float copy for long lines)
   if constexpr (sizeof(LT) == 4) eline = a.eps32;
   else eline = a.eps;
@@ -414,6 +419,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   };
 
   int ql = 0;  // q-lines started in this launch
+  const LT *nline = eline;  // energies of the next q-line
   for (int q3 = a.q3_lo; q3 < a.q3_hi; q3++) {
     // ---- Y_s(p1, p2; q3) into registers (p3 loop rolled) ----
 #pragma unroll
@@ -468,11 +474,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
         }
         const int n2l = (k2 + nq2 >= N) ? k2 + nq2 - N : k2 + nq2;
         const int n3l = (k3 + nq3 >= N) ? k3 + nq3 - N : k3 + nq3;
-        const LT *ln = eline + (size_t)(n2l + N * n3l) * LN;
+        nline = eline + (size_t)(n2l + N * n3l) * LN;
+        if constexpr (PF) {
 #pragma unroll
-        for (int i = 0; i < LPL; i++) {
-          const int e = lane + 64 * i;
-          nxt[i] = (e < LN) ? ln[e] : (LT)0;
+          for (int i = 0; i < LPL; i++) {
+            const int e = lane + 64 * i;
+            nxt[i] = (e < LN) ? nline[e] : (LT)0;
+          }
         }
       }
       // ---- Z_s(p1; q2, q3) -> LDS slot ----
@@ -538,10 +546,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
       __syncwarp();
       // stage the next line's energies ([m][p1] in LDS); the scan of this
       // line is done, and the drains read energies from global memory
+      if constexpr (PF) {
 #pragma unroll
-      for (int i = 0; i < LPL; i++) {
-        const int e = lane + 64 * i;
-        if (e < LN) sLine[(e % NW) * N + e / NW] = (LT)nxt[i];
+        for (int i = 0; i < LPL; i++) {
+          const int e = lane + 64 * i;
+          if (e < LN) sLine[(e % NW) * N + e / NW] = (LT)nxt[i];
+        }
+      } else {
+        for (int e = lane; e < LN; e += 64) sLine[(e % NW) * N + e / NW] = nline[e];
       }
       __syncwarp();
     }

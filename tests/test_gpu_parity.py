@@ -222,3 +222,31 @@ def test_al_fcc_long_lines_k_subset(torch_cuda):
     c = g["counts"]
     assert c["n_kq"] == r["n_kq"] and c["n_terms"] == int(r["n_terms"].sum())
     ctx.close()
+
+
+def test_very_long_lines_k_subset(torch_cuda):
+    """Lines longer than 1024 energies (8 orbitals, N = 130: 1040) take the
+    kernel variant that copies each line at its staging point instead of
+    prefetching it into registers; two seeded k points against the oracle."""
+    from paper_2306_16493_amd import Context
+    s = make_system("mini_w8")
+    o = Oracle(s)
+    N, eta, temps = 130, 0.02, [300.0]
+    mu = s.mu_centroid
+    lo, hi = mu - 0.3, mu + 0.3
+    eps, evec, vel = o.electrons(N)
+    sk_all, _ = o.select_states(eps, 0, s.nw - 1, lo, hi)
+    rng = np.random.default_rng(1649313 + 1)
+    kpick = np.sort(rng.choice(np.unique(sk_all), size=2, replace=False))
+    ctx = Context(s)
+    p = ctx.params(N, mu, temps, eta, lo, hi, k_subset=kpick)
+    log(f"[parity] mini_w8 N={N} (lines of {N * s.nw} energies), {len(kpick)} k points")
+    g = gpu_run(ctx, p)
+    om, u, _ = o.phonons(N)
+    sk, sn = o.select_states(eps, 0, s.nw - 1, lo, hi, k_subset=kpick)
+    r = o.rates(N, eps, evec, om, u, sk, sn, mu, temps, eta)
+    assert np.array_equal(g["state_k"], sk) and np.array_equal(g["state_n"], sn)
+    compare_rates(g, r["inv_tau"], eps, sk, sn)
+    c = g["counts"]
+    assert c["n_kq"] == r["n_kq"] and c["n_terms"] == int(r["n_terms"].sum())
+    ctx.close()
