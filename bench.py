@@ -89,7 +89,7 @@ def main():
                          "surrogate)")
     ap.add_argument("--grid", type=int, default=None)
     ap.add_argument("--precision", default="fp64")
-    ap.add_argument("--cpu-sample", type=int, default=16, help="k points of the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=40, help="k points of the oracle sample (0 = skip)")
     ap.add_argument("--report", choices=["precision", "surrogate"], default=None,
                     help="instead of the bench line, measure the FP32/BF16x3 forms or the surrogate on "
                          "their own workloads (one JSON line)")
