@@ -161,10 +161,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 
   // final-state line energies: the next q-line's are loaded into registers
   // while the current one (in LDS, [m][p1]) is scanned
-  // lines up to 1024 energies are prefetched into registers while a line is
-  // worked on; longer ones are copied at the staging point (their registers
-  // would push the kernel into spilling)
-  constexpr bool PF = LPL <= 16;
+  // lines are prefetched into registers while a line is worked on up to 1024
+  // energies in FP32 and 512 in FP64 (where registers are scarcer); longer
+  // ones are copied at the staging point, since the prefetch registers would
+  // push the kernel into spilling
+  constexpr bool PF = LPL <= (sizeof(T) == 8 ? 8 : 16);
   constexpr int LPR = PF ? LPL : 1;
   LT nxt[LPR];
   const LT *eline;  // energy table the prefilter reads (FP64, or its float copy for long lines)
