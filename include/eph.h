@@ -35,6 +35,8 @@
  *   - A context is used by one host thread at a time.  Calls enqueue their
  *     work on the given HIP stream (NULL = the default stream) and
  *     synchronise that stream before they return host results.
+ *   - Calls make the context's device current while they run and restore
+ *     the caller's current device before they return.
  */
 #ifndef EPH_H
 #define EPH_H
@@ -68,10 +70,11 @@ typedef enum {
 } eph_precision;
 
 /* Limits of this implementation (EPH_E_UNSUPPORTED beyond them). */
-#define EPH_MAX_WANN 8   /* Wannier orbitals: 1, 2, 4 or 8 */
-#define EPH_MAX_MODES 6  /* phonon modes 3*n_atoms: 3 or 6 */
-#define EPH_MAX_TEMPS 4  /* temperatures per rates call */
-#define EPH_MAX_GRID 512 /* N of the N x N x N grid */
+#define EPH_MAX_WANN 8    /* Wannier orbitals: 1, 2, 4 or 8 */
+#define EPH_MAX_MODES 6   /* phonon modes 3*n_atoms: 3 or 6 */
+#define EPH_MAX_TEMPS 4   /* temperatures per rates call */
+#define EPH_MAX_GRID 512  /* N of the N x N x N grid */
+#define EPH_MAX_LINE 2048 /* N * n_wann: energies on one final-state line */
 
 /* The Wannier-basis model.  All pointers are HOST pointers; the data is
  * copied to the device by eph_load_wannier and the caller keeps ownership.
@@ -141,6 +144,13 @@ typedef struct {
                                states are computed (duplicates ignored);
                                NULL = every k of the grid */
   int64_t n_k_subset;
+  int64_t mem_budget_bytes; /* device workspace this call may use (grid
+                               tables, state lists, per-batch buffers);
+                               the states are processed in batches sized
+                               to fit.  0 = automatic (per-batch buffers up
+                               to 8 GiB).  EPH_E_NOMEM, with the required
+                               size in eph_last_error, when the tables and
+                               one group of states do not fit. */
   void *stream;             /* hipStream_t, NULL = default stream */
 } eph_rates_params;
 

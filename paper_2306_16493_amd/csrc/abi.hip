@@ -96,6 +96,40 @@ hipError_t upload(DevBuf &b, const T *host, size_t n) {
   return hipMemcpy(b.p, host, sizeof(T) * n, hipMemcpyHostToDevice);
 }
 
+// Device workspace of one rates call: grid tables and per-call lists
+// (fixed), and the per-batch buffers per state of a batch.
+struct Workspace {
+  size_t fixed = 0;
+  size_t per_state = 0;
+};
+
+Workspace plan_workspace(const eph_ctx *c, int N, int precision, int64_t nkl, int64_t ns, bool wave) {
+  const size_t NQ = (size_t)N * N * N, nw = c->nw, nm = c->nm;
+  const bool red = precision != EPH_FP64;
+  Workspace w;
+  size_t t = 16 * (size_t)N + 64;                                   // phase table, counters
+  t += NQ * nw * 8 + NQ * nw * nw * 16 + NQ * nw * 24;              // eps, eigenvectors, velocities
+  t += NQ * nm * 8 + NQ * nm * nm * 16;                             // phonon energies, displacements
+  if (red) t += NQ * nw * nw * 8 + NQ * nm * nm * 8;                // FP32 rotation tables
+  const size_t ncol = (size_t)c->box.count() * nm * nw, K = (size_t)c->nre * nw;
+  if (precision == EPH_FP32) t += ncol * K * 8;                     // FP32 copy of g
+  if (precision == EPH_BF16X3) t += 4 * bf16_w_elems(c->nre, c->nw, (int)ncol);  // bf16 hi/lo of g
+  if (wave) {
+    t += NQ * (nw + nm) * EPH_MAX_TEMPS * 8;                        // occupation tables
+    if ((size_t)N * nw > 512) t += NQ * nw * 4;                     // float energies of long lines
+  } else {
+    t += NQ * nw * 10;                                              // energy-sorted lines
+  }
+  const size_t nl = (size_t)nkl + 1;
+  t += 8 * (nl * 2 + scan_tmp_elems((int64_t)nl));                  // state counts and offsets
+  t += 8 * (size_t)nkl;                                             // k subset
+  const size_t nsl = (size_t)ns + 1;
+  t += 8 * (3 * nsl + 2 * (size_t)ns + scan_tmp_elems((int64_t)nsl));  // groups, per-state counts
+  w.fixed = t;
+  w.per_state = (size_t)c->box.count() * nm * nw * (red ? 8 : 16);  // X row
+  return w;
+}
+
 // Checks that the R set is closed under negation with equal weights and
 // that M(-R) = M(R)^dagger (herm=true, complex) or M(R)^T (real).
 std::string check_pairs(int nr, const int32_t *R, const double *w, const double *M, int n, bool cplx) {
@@ -212,7 +246,8 @@ int32_t eph_load_wannier(const eph_model *m, int32_t device, eph_ctx **out) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return bad(EPH_E_DEVICE, "no HIP device");
   if (device < 0 || device >= ndev) return bad(EPH_E_INVALID, "device index out of range");
-  if (hipSetDevice(device) != hipSuccess) return bad(EPH_E_DEVICE, "hipSetDevice failed");
+  DeviceGuard dg(device);
+  if (!dg.ok) return bad(EPH_E_DEVICE, "hipSetDevice failed");
 
   c->device = device;
   c->nw = nw;
@@ -282,6 +317,8 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
   const int N = p->grid[0];
   if (N < 1 || p->grid[1] != N || p->grid[2] != N) return fail(c, EPH_E_INVALID, "grid must be N x N x N, N >= 1");
   if (N > EPH_MAX_GRID) return fail(c, EPH_E_UNSUPPORTED, "grid above EPH_MAX_GRID");
+  if ((int64_t)N * c->nw > EPH_MAX_LINE) return fail(c, EPH_E_UNSUPPORTED, "N * n_wann above EPH_MAX_LINE");
+  if (p->mem_budget_bytes < 0) return fail(c, EPH_E_INVALID, "mem_budget_bytes < 0");
   if (p->n_temps < 1 || p->n_temps > EPH_MAX_TEMPS || !p->temps_K)
     return fail(c, EPH_E_INVALID, "n_temps must be 1..EPH_MAX_TEMPS with temps_K given");
   for (int t = 0; t < p->n_temps; t++)
@@ -308,10 +345,21 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     std::sort(klist.begin(), klist.end());
     klist.erase(std::unique(klist.begin(), klist.end()), klist.end());
   }
-  if (hipSetDevice(c->device) != hipSuccess) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  const int nw = c->nw, nm = c->nm;
+  const int gwave = rates_wave_group(nw, nm, c->box, N, p->precision);
+  if (gwave == 0 && rates_smem_bytes(p->precision, N, nw, nm, c->box) > 160 * 1024)
+    return fail(c, EPH_E_UNSUPPORTED, "Rp box too large for the workgroup rate kernel at this grid");
+  const int64_t nkl = p->k_subset ? (int64_t)klist.size() : (int64_t)N * N * N;
+  {  // the grid tables and lists alone must fit the budget (states not known yet)
+    const Workspace w0 = plan_workspace(c, N, p->precision, nkl, 0, gwave > 0);
+    if (p->mem_budget_bytes > 0 && w0.fixed > (size_t)p->mem_budget_bytes)
+      return fail(c, EPH_E_NOMEM, "mem_budget_bytes below the grid tables and lists (" + std::to_string(w0.fixed) +
+                                      " bytes)");
+  }
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = static_cast<hipStream_t>(p->stream);
   const Units U = units();
-  const int nw = c->nw, nm = c->nm;
   Timer tm{c, st};
   int e_start, e_tables = -1, e_prep = -1, e_end;
   std::vector<int> e_batch;  // per batch: before transform, after transform, after rates
@@ -359,7 +407,6 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
   EPH_HIP(c, tm.mark(&e_tables));
 
   // ---- states in the window ----
-  const int64_t nkl = p->k_subset ? (int64_t)klist.size() : NQ;
   const int64_t *d_klist = nullptr;
   if (p->k_subset) {
     EPH_HIP(c, c->subset.ensure(sizeof(int64_t) * std::max<int64_t>(1, nkl)));
@@ -393,16 +440,22 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
 
   if (ns > 0) {
     // ---- groups of states sharing a k-line ----
-    // kernel choice: staged q-line form, else wave-autonomous, else workgroup form
-    // EPH_RATES_KERNEL=stage|wave|group selects a form (for measurements); the
-    // default is the wave-autonomous form where it applies
-    const char *kc = std::getenv("EPH_RATES_KERNEL");
-    const std::string ks = kc ? kc : "";
-    const bool allow_stage = ks == "stage", allow_wave = ks.empty() || ks == "wave";
-    const int gstage =
-        (allow_stage && p->precision == EPH_FP64) ? rates_stage_group(nw, nm, c->box, N, p->n_temps) : 0;
-    const int gwave = (gstage > 0 || !allow_wave) ? 0 : rates_wave_group(nw, nm, c->box, N, p->precision);
-    const int gmax = gstage > 0 ? gstage : gwave > 0 ? gwave : rates_group_max(nw, nm);
+    // the wave-autonomous kernel where it applies, else the workgroup form
+    const int gmax = gwave > 0 ? gwave : rates_group_max(nw, nm);
+    // state batches: the per-batch buffers (X) within the budget
+    const Workspace ws = plan_workspace(c, N, p->precision, nkl, ns, gwave > 0);
+    int64_t max_states;
+    if (p->mem_budget_bytes > 0) {
+      const size_t need = ws.fixed + ws.per_state * (size_t)gmax;
+      if (need > (size_t)p->mem_budget_bytes)
+        return fail(c, EPH_E_NOMEM, "mem_budget_bytes below the minimum of " + std::to_string(need) + " bytes (" +
+                                        std::to_string(ws.fixed) + " bytes of tables and lists plus " +
+                                        std::to_string(ws.per_state) + " bytes per state of a batch, " +
+                                        std::to_string(gmax) + " states per group)");
+      max_states = (int64_t)(((size_t)p->mem_budget_bytes - ws.fixed) / ws.per_state);
+    } else {
+      max_states = std::max<int64_t>(gmax, (int64_t)(((size_t)8 << 30) / ws.per_state));
+    }
     EPH_HIP(c, c->grp_tmp.ensure(sizeof(int64_t) * 2 * (ns + 1)));
     int64_t *flag = c->grp_tmp.as<int64_t>(), *pos = flag + ns + 1;
     EPH_HIP(c, c->scan_tmp.ensure(sizeof(int64_t) * std::max(scan_tmp_elems(nkl + 1), scan_tmp_elems(ns))));
@@ -419,8 +472,9 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     std::vector<int64_t> hg(ng + 1);
     EPH_HIP(c, hipMemcpyAsync(hg.data(), gstart, sizeof(int64_t) * (ng + 1), hipMemcpyDeviceToHost, st));
 
-    // ---- energy-sorted final-state lines; largest phonon energy ----
-    if (gwave == 0 && gstage == 0) {
+    // ---- energy-sorted final-state lines (workgroup form) or occupation
+    //      tables (wave form); largest phonon energy ----
+    if (gwave == 0) {
       EPH_HIP(c, c->line_e.ensure(sizeof(double) * NQ * nw));
       EPH_HIP(c, c->line_key.ensure(sizeof(uint16_t) * NQ * nw));
       EPH_HIP(c, launch_line_sort(N, nw, c->eps.as<double>(), c->line_e.as<double>(), c->line_key.as<uint16_t>(),
@@ -432,13 +486,6 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
       EPH_HIP(c, launch_occupations(NQ, nw, nm, c->eps.as<double>(), c->om.as<double>(), p->mu_eV, p->n_temps, kts,
                                     p->omega_cut_eV, c->occ.as<double>(),
                                     c->occ.as<double>() + (size_t)NQ * nw * EPH_MAX_TEMPS, st));
-      if (gstage > 0) {
-        EPH_HIP(c, c->packed.ensure(sizeof(double) * stage_table_words(NQ, nw, nm, p->n_temps)));
-        EPH_HIP(c, launch_pack_tables(NQ, nw, nm, p->n_temps, c->eps.as<double>(), c->om.as<double>(),
-                                      c->evec.as<double2>(), c->uu.as<double2>(), c->occ.as<double>(),
-                                      c->occ.as<double>() + (size_t)NQ * nw * EPH_MAX_TEMPS, c->packed.as<double>(),
-                                      c->packed.as<double>() + stage_table_words(NQ, 0, nm, p->n_temps), st));
-      }
     }
     EPH_HIP(c, launch_max_nonneg(NQ * nm, c->om.as<double>(), ctr + 1, st));
     EPH_HIP(c, tm.mark(&e_prep));
@@ -449,9 +496,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     std::memcpy(&wmax, &wbits, sizeof(wmax));
 
     // ---- per batch of groups: Re transform, then the fused rate kernel ----
-    const size_t xrow = (size_t)c->box.count() * nm * nw * (fp32 ? sizeof(float2) : sizeof(double2));
-    const size_t budget = (size_t)8 << 30;
-    int64_t max_states = std::max<int64_t>(gmax, (int64_t)(budget / xrow));
+    const size_t xrow = ws.per_state;
     EPH_HIP(c, c->state_cnt.ensure(sizeof(int64_t) * 2 * ns));
     RatesArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -517,10 +562,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
       a.s_base = sa;
       a.X = c->xbuf.p;
       EPH_HIP(c, tm.mark(&eb1));
-      if (gstage > 0)
-        EPH_HIP(c, launch_rates_stage(a, c->packed.as<double>(),
-                                      c->packed.as<double>() + stage_table_words(NQ, 0, nm, p->n_temps), st));
-      else if (gwave > 0) {
+      if (gwave > 0) {
         // one launch per q3 plane: every resident wave then works on the same
         // plane, whose q-side tables stay in the XCD's L2
         for (int q3 = 0; q3 < N; q3++) {
@@ -534,7 +576,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
       EPH_HIP(c, tm.mark(&eb2));
       e_batch.insert(e_batch.end(), {eb0, eb1, eb2});
       c->launches[0]++;
-      c->launches[1] += (gstage == 0 && gwave > 0) ? N : 1;
+      c->launches[1] += gwave > 0 ? N : 1;
       g0 = g1;
     }
     EPH_HIP(c, launch_summarize(ns, c->state_cnt.as<int64_t>(), inv_tau_s, ctr + 3, st));
@@ -604,7 +646,8 @@ int32_t moments(eph_ctx *c, int64_t n_states, const double *energy_eV, const dou
   if (n_kpoints < 1) return fail(c, EPH_E_INVALID, "n_kpoints must be >= 1");
   if (n_states > 0 && (!energy_eV || !vel_ms || !inv_tau_s)) return fail(c, EPH_E_INVALID, "NULL input buffer");
   if (!std::isfinite(mu_eV)) return fail(c, EPH_E_INVALID, "mu must be finite");
-  if (hipSetDevice(c->device) != hipSuccess) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Units U = units();
   const int nblk = 256;
@@ -694,7 +737,8 @@ int32_t eph_carrier_density(eph_ctx *c, int32_t grid, int32_t band_lo, int32_t b
     if (!(temps_K[t] > 0.0) || !std::isfinite(temps_K[t])) return fail(c, EPH_E_INVALID, "temperatures must be > 0");
   if (!std::isfinite(mu_eV)) return fail(c, EPH_E_INVALID, "mu must be finite");
   if (!n_per_m3) return fail(c, EPH_E_INVALID, "output is NULL");
-  if (hipSetDevice(c->device) != hipSuccess) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Units U = units();
   const int N = grid, nw = c->nw;

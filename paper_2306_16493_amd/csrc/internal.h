@@ -18,6 +18,7 @@ constexpr double kCharge = 1.602176634e-19;
 constexpr double kBoltz = 1.380649e-23;
 constexpr double kAmu = 1.66053906892e-27;
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxLine = EPH_MAX_LINE;
 
 struct Units {
   double hbar_evs;   // hbar in eV s
@@ -27,6 +28,20 @@ struct Units {
   double rate_pref;  // 2 pi / hbar in 1/(eV s)
 };
 Units units();
+
+// Makes a device current for the lifetime of the guard and restores the
+// caller's current device afterwards.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -77,7 +92,6 @@ struct eph_ctx {
   eph::DevBuf sig_part;                 // sigma partial sums
   eph::DevBuf state_cnt;                // per-state int64 counts
   eph::DevBuf occ;                      // Fermi and Bose factor tables
-  eph::DevBuf packed;                   // packed q-side / p-side records
   // stage timing
   bool profiling = false;
   std::vector<hipEvent_t> ev;  // created on demand, reused across calls
@@ -173,13 +187,6 @@ hipError_t launch_rates(int precision, const RatesArgs &a, hipStream_t st);
 // (0 when the shape is not served and launch_rates must be used).
 int rates_wave_group(int nw, int nm, RpBox box, int N, int precision);
 hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st);
-// Staged q-line rate kernel (FP64): states per group, 0 when not served.
-int rates_stage_group(int nw, int nm, RpBox box, int N, int nt);
-size_t stage_table_words(int64_t nq, int nw, int nm, int nt);
-hipError_t launch_pack_tables(int64_t nq, int nw, int nm, int nt, const double *eps, const double *om,
-                              const double2 *evec, const double2 *uu, const double *occ_f, const double *occ_n,
-                              double *qt, double *pt, hipStream_t st);
-hipError_t launch_rates_stage(const RatesArgs &a, const double *qt, const double *pt, hipStream_t st);
 // Occupation tables: occ_f[k][n][t] = 1/(exp((eps-mu)/kT_t)+1),
 // occ_n[q][nu][t] = 1/expm1(hbar w/kT_t) (0 when hbar w < wcut).
 hipError_t launch_occupations(int64_t nq, int nw, int nm, const double *eps, const double *om, double mu,

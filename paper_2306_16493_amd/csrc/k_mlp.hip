@@ -485,7 +485,8 @@ int32_t eph_mlp_create(eph_ctx *ctx, int32_t n_members, int32_t n_out, uint64_t 
     ctx->err = "n_members must be 1..64 and n_out 1..EPH_MAX_TEMPS";
     return EPH_E_INVALID;
   }
-  if (hipSetDevice(ctx->device) != hipSuccess) return EPH_E_DEVICE;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return EPH_E_DEVICE;
   eph_mlp *m = new eph_mlp();
   m->ctx = ctx;
   m->members = n_members;
@@ -514,12 +515,18 @@ int32_t eph_mlp_create(eph_ctx *ctx, int32_t n_members, int32_t n_out, uint64_t 
   return EPH_OK;
 }
 
-void eph_mlp_free(eph_mlp *m) { delete m; }
+void eph_mlp_free(eph_mlp *m) {
+  if (!m) return;
+  DeviceGuard dg(m->ctx->device);
+  delete m;
+}
 
 int32_t eph_mlp_params(eph_mlp *m, float *host, int64_t *n_params_out, int32_t set) {
   if (!m) return EPH_E_INVALID;
   if (n_params_out) *n_params_out = m->P;
   if (!host) return EPH_OK;
+  DeviceGuard dg(m->ctx->device);
+  if (!dg.ok) return EPH_E_DEVICE;
   const size_t bytes = 4 * (size_t)m->members * m->P;
   MHIP(m, set ? hipMemcpy(m->params.p, host, bytes, hipMemcpyHostToDevice)
               : hipMemcpy(host, m->params.p, bytes, hipMemcpyDeviceToHost));
@@ -532,6 +539,8 @@ int32_t eph_mlp_features(eph_ctx *ctx, int64_t n, const int32_t *state_k, const 
   if (!ctx || n < 0 || grid < 1 || (n > 0 && (!state_k || !energy || !vel || !x))) return EPH_E_INVALID;
   if (inv_tau && (!y || nt < 1 || nt > MAXOUT)) return EPH_E_INVALID;
   if (n == 0) return EPH_OK;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return EPH_E_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, state_k, energy,
                      vel, grid, mu, inv_tau, nt, x, y);
@@ -548,6 +557,8 @@ int32_t eph_mlp_train(eph_mlp *m, int64_t n, const float *x, const float *y, int
   if (!m) return EPH_E_INVALID;
   if (n < 1 || !x || !y || steps < 0 || batch < TS || batch % TS || !(lr > 0.0f))
     return mfail(m, EPH_E_INVALID, "train: n >= 1, batch a positive multiple of 32, lr > 0");
+  DeviceGuard dg(m->ctx->device);
+  if (!dg.ok) return EPH_E_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!m->normalised) {  // statistics of the first training set define the normalisation
     hipLaunchKernelGGL(mlp_norm_kernel, dim3(NIN + m->nout), dim3(256), 0, st, n, m->nout, x, y, m->norm.as<float>());
@@ -584,6 +595,8 @@ int32_t eph_mlp_train(eph_mlp *m, int64_t n, const float *x, const float *y, int
 int32_t eph_mlp_gradient(eph_mlp *m, int64_t n, const float *x, const float *y, float *grad_host,
                          float *loss_host) {
   if (!m || n < TS || n % TS || !x || !y || !grad_host) return EPH_E_INVALID;
+  DeviceGuard dg(m->ctx->device);
+  if (!dg.ok) return EPH_E_DEVICE;
   const int tiles = (int)(n / TS);
   int r = run_fwdbwd(m, n, x, y, tiles, -1, 0);
   if (r != EPH_OK) return r;
@@ -606,6 +619,8 @@ int32_t eph_mlp_predict(eph_mlp *m, int64_t n, const float *x, float *y, void *s
   if (!m || n < 0 || (n > 0 && (!x || !y))) return EPH_E_INVALID;
   if (!m->normalised) return mfail(m, EPH_E_STATE, "predict before train");
   if (n == 0) return EPH_OK;
+  DeviceGuard dg(m->ctx->device);
+  if (!dg.ok) return EPH_E_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((n + TS - 1) / TS), m->members), dim3(THREADS), 0, st,
                      m->nout, n, x, m->params.as<float>(), m->norm.as<float>(), y);
@@ -616,6 +631,8 @@ int32_t eph_mlp_predict(eph_mlp *m, int64_t n, const float *x, float *y, void *s
 int32_t eph_mlp_blend(eph_mlp *m, int64_t n, const float *y, double threshold, double *inv_tau, int32_t *flag,
                       int64_t *n_flagged, void *stream) {
   if (!m || n < 0 || (n > 0 && (!y || !inv_tau || !flag))) return EPH_E_INVALID;
+  DeviceGuard dg(m->ctx->device);
+  if (!dg.ok) return EPH_E_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   MHIP(m, launch_zero(m->nflag.p, 8, st));
   if (n > 0) {
@@ -636,6 +653,8 @@ int32_t eph_merge_rates(eph_ctx *ctx, int64_t n_full, const int32_t *full_k, con
   if (!ctx || n_full < 0 || n_sub < 0 || nt < 1 || nt > MAXOUT) return EPH_E_INVALID;
   if (n_sub == 0) return EPH_OK;
   if (!full_k || !full_n || !sub_k || !sub_n || !sub_inv_tau || !full_inv_tau) return EPH_E_INVALID;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return EPH_E_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((n_sub + 255) / 256)), dim3(256), 0, st, n_full, full_k, full_n,
                      n_sub, sub_k, sub_n, nt, sub_inv_tau, full_inv_tau);

@@ -1,0 +1,8 @@
+// Wave-autonomous rate kernel instances: FP64 transforms, 3 phonon modes.
+#include "rates_wave.h"
+
+namespace eph {
+namespace wave {
+template hipError_t dispatch_nm<double, 3>(const RatesArgs &, hipStream_t);
+}  // namespace wave
+}  // namespace eph

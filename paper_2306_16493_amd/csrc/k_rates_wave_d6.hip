@@ -1,0 +1,8 @@
+// Wave-autonomous rate kernel instances: FP64 transforms, 6 phonon modes.
+#include "rates_wave.h"
+
+namespace eph {
+namespace wave {
+template hipError_t dispatch_nm<double, 6>(const RatesArgs &, hipStream_t);
+}  // namespace wave
+}  // namespace eph

@@ -49,7 +49,8 @@ class RatesParams(C.Structure):
                 ("temps_K", C.c_void_p), ("eta_eV", C.c_double), ("sieve_width", C.c_double),
                 ("win_lo_eV", C.c_double), ("win_hi_eV", C.c_double), ("band_lo", C.c_int32),
                 ("band_hi", C.c_int32), ("omega_cut_eV", C.c_double), ("precision", C.c_int32),
-                ("k_subset", C.c_void_p), ("n_k_subset", C.c_int64), ("stream", C.c_void_p)]
+                ("k_subset", C.c_void_p), ("n_k_subset", C.c_int64), ("mem_budget_bytes", C.c_int64),
+                ("stream", C.c_void_p)]
 
 
 class Counts(C.Structure):
@@ -182,7 +183,7 @@ class Context:
 
     @staticmethod
     def params(grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, sieve_width=6.0,
-               omega_cut=1e-4, precision="fp64", k_subset=None, stream=None):
+               omega_cut=1e-4, precision="fp64", k_subset=None, stream=None, mem_budget_bytes=0):
         p = RatesParams()
         p.grid[0] = p.grid[1] = p.grid[2] = int(grid)
         p.mu_eV = float(mu)
@@ -204,6 +205,7 @@ class Context:
             p.k_subset, p.n_k_subset = _ptr(ks), n
         else:
             p.k_subset, p.n_k_subset = None, 0
+        p.mem_budget_bytes = int(mem_budget_bytes)
         p.stream = C.c_void_p(stream) if stream else None
         p._keep = keep
         return p

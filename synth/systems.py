@@ -61,6 +61,14 @@ def lattice_block(n: int) -> np.ndarray:
     return g.astype(np.int32)
 
 
+def lattice_box(n1: int, n2: int, n3: int) -> np.ndarray:
+    """n1 x n2 x n3 integer vectors, each coordinate centred as in
+    lattice_block, first coordinate slowest."""
+    axes = [np.arange(-((n - 1) // 2), -((n - 1) // 2) + n) for n in (n1, n2, n3)]
+    g = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    return g.astype(np.int32)
+
+
 def ws_block(n: int) -> Tuple[np.ndarray, np.ndarray]:
     """(n+1)^3 vectors {-n/2..n/2}^3 (n even) with weight 1/2 per boundary
     coordinate; closed under negation, weights sum to n^3."""
@@ -188,9 +196,19 @@ def make_system(name: str, seed: Optional[int] = None, real_g: bool = False) -> 
               small models covering the other (orbitals, modes) shapes:
               1 or 8 orbitals with 1 atom, 2 or 4 orbitals with 2 atoms;
               every block 4^3
+    'box5_w4', 'box446_w2a2'
+              small models whose Rp set is a 5^3 box (4 orbitals, 1 atom)
+              or a 4 x 4 x 6 box (2 orbitals, 2 atoms)
+    'degen_w4', 'degen_w4_sym'
+              exactly degenerate model: H(R) = h(R) (x) I_2 with a random
+              2-orbital h (every band 2-fold), one atom with isotropic
+              nearest-neighbour springs on a simple-cubic lattice (every
+              phonon 3-fold); g random ('degen_w4') or g'(x) I_2
+              ('degen_w4_sym', two identical decoupled copies)
     """
     defaults = {"toy_sc": 1649301, "al_fcc": 1649302, "si_fcc": 1649303,
-                "mini_w1": 1649311, "mini_w2a2": 1649312, "mini_w8": 1649313, "mini_w4a2": 1649314}
+                "mini_w1": 1649311, "mini_w2a2": 1649312, "mini_w8": 1649313, "mini_w4a2": 1649314,
+                "box5_w4": 1649315, "box446_w2a2": 1649316, "degen_w4": 1649317, "degen_w4_sym": 1649317}
     if seed is None:
         seed = defaults[name]
     rng = np.random.default_rng(seed)
@@ -221,6 +239,45 @@ def make_system(name: str, seed: Optional[int] = None, real_g: bool = False) -> 
         mass = np.array([26.98, 40.0])
         nw = 2 if name == "mini_w2a2" else 4
         nh, nd, ne, npv, onsite = 4, 4, 4, 4, None
+    elif name in ("box5_w4", "box446_w2a2"):
+        if name == "box5_w4":
+            lat, tau, mass, nw = _sc(3.0), np.zeros((1, 3)), np.array([26.98]), 4
+        else:
+            a = 3.5
+            lat = _sc(a)
+            tau = np.array([[0.0, 0.0, 0.0], [0.5 * a, 0.5 * a, 0.5 * a]])
+            mass, nw = np.array([26.98, 40.0]), 2
+        rh, rh_w = ws_block(4)
+        rd, rd_w = ws_block(4)
+        re = lattice_block(4)
+        rp = lattice_block(5) if name == "box5_w4" else lattice_box(4, 4, 6)
+        ham = _draw_ham(rng, lat, rh, nw)
+        ifc = _draw_ifc(rng, lat, tau, mass, rd, rd_w, 0.040)
+        gw = _draw_g(rng, lat, re, rp, 3 * mass.shape[0], nw)
+        i0 = int(np.where((rh == 0).all(axis=1))[0][0])
+        return System(name, lat, tau, mass, nw, rh, rh_w, ham, rd, rd_w, ifc, re, rp, gw,
+                      float(np.real(np.trace(ham[i0]))) / nw)
+    elif name in ("degen_w4", "degen_w4_sym"):
+        lat, tau, mass = _sc(3.0), np.zeros((1, 3)), np.array([26.98])
+        rh, rh_w = ws_block(4)
+        h = _draw_ham(rng, lat, rh, 2)
+        ham = np.stack([np.kron(hr, np.eye(2)) for hr in h]).astype(np.complex128)
+        # isotropic nearest-neighbour springs: Phi(+-a_i) = -K I, Phi(0) = 6K I
+        rd = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.int32)
+        rd_w = np.ones(rd.shape[0])
+        K = 1.0
+        ifc = np.stack([6 * K * np.eye(3)] + [-K * np.eye(3)] * 6)
+        # scale so that the largest phonon energy (q = (1/2,1/2,1/2)) is 40 meV
+        ifc = ifc * (0.040 ** 2 / (_c_phonon_ev() * 12 * K / mass[0]))
+        re, rp = lattice_block(4), lattice_block(4)
+        if name == "degen_w4":
+            gw = _draw_g(rng, lat, re, rp, 3, 4)
+        else:
+            g2 = _draw_g(rng, lat, re, rp, 3, 2)
+            gw = np.einsum("abmij,kl->abmikjl", g2, np.eye(2)).reshape(re.shape[0], rp.shape[0], 3, 4, 4)
+        i0 = int(np.where((rh == 0).all(axis=1))[0][0])
+        return System(name, lat, tau, mass, 4, rh, rh_w, ham, rd, rd_w, ifc.astype(np.float64), re, rp,
+                      gw.astype(np.complex128), float(np.real(np.trace(ham[i0]))) / 4)
     else:
         raise KeyError(name)
     rh, rh_w = ws_block(nh)

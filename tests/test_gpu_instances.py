@@ -1,0 +1,226 @@
+"""Parity of the rate-kernel instances that the large workloads run, of the
+workgroup form, of exactly degenerate bands and of the batched path, each
+against the FP64 oracle through the C ABI.
+
+Tolerances: FP64 1e-10 relative per state (group sums for degenerate
+groups) and for sigma; the reduced-precision forms 1e-4 per state and in
+sigma (the acceptance bound for sigma is 1e-3); integer counts exact.
+"""
+import re
+
+import numpy as np
+import pytest
+
+from gpu_helpers import log, params_for, gpu_run, compare_rates, rel_err
+from synth import make_system, workload
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+TOL_RED = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _subset_case(system, N, eta, temps, window, band_lo, band_hi, nk, seed):
+    """Oracle tables on the full N^3 grid and the oracle's rates for a seeded
+    set of nk k points that carry window states."""
+    s = make_system(system)
+    o = Oracle(s)
+    log(f"  oracle tables {system} N={N} ...")
+    eps, evec, vel = o.electrons(N)
+    om, u, _ = o.phonons(N)
+    lo, hi = window(eps)
+    sk_all, _ = o.select_states(eps, band_lo, band_hi, lo, hi)
+    rng = np.random.default_rng(seed)
+    kpick = np.sort(rng.choice(np.unique(sk_all), size=nk, replace=False))
+    sk, sn = o.select_states(eps, band_lo, band_hi, lo, hi, k_subset=kpick)
+    log(f"  oracle rates for {len(sk)} states at {nk} k points ...")
+    return dict(s=s, eps=eps, evec=evec, om=om, u=u, lo=lo, hi=hi, kpick=kpick, sk=sk, sn=sn)
+
+
+@pytest.fixture(scope="module")
+def si_long_lines(torch_cuda):
+    """Si-like (8 orbitals, 2 atoms, Rp 6^3) at N = 130: lines of 1040
+    energies, the kernel instance of the 150^3 and 200^3 Si-like workloads."""
+    w = workload("si_fcc_150", 130)
+    N = 130
+
+    def window(eps):
+        cbm = eps[:, 4].min()
+        return cbm - 1e-7, cbm + 0.25
+
+    c = _subset_case("si_fcc", N, w.eta, w.temps, window, w.band_lo, w.band_hi, 8, 1649303 + 21)
+    mu = c["eps"][:, 4].min() - 0.25
+    r = Oracle(c["s"]).rates(N, c["eps"], c["evec"], c["om"], c["u"], c["sk"], c["sn"], mu, w.temps, w.eta)
+    c.update(N=N, mu=mu, w=w, r=r)
+    return c
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_si_like_long_line_instance(si_long_lines, prec):
+    from paper_2306_16493_amd import Context
+    c = si_long_lines
+    w, N = c["w"], c["N"]
+    ctx = Context(c["s"])
+    p = ctx.params(N, c["mu"], w.temps, w.eta, c["lo"], c["hi"], w.band_lo, w.band_hi, precision=prec,
+                   k_subset=c["kpick"])
+    log(f"[instance] si_fcc N={N} ({N * 8} energies per line) {prec}, {len(c['kpick'])} k points")
+    g = gpu_run(ctx, p)
+    assert np.array_equal(g["state_k"], c["sk"]) and np.array_equal(g["state_n"], c["sn"])
+    compare_rates(g, c["r"]["inv_tau"], c["eps"], c["sk"], c["sn"], tol=TOL if prec == "fp64" else TOL_RED)
+    cnt = g["counts"]
+    assert cnt["n_kq"] == c["r"]["n_kq"] and cnt["n_terms"] == int(c["r"]["n_terms"].sum())
+    assert cnt["n_nkq"] == int(c["r"]["n_q_valid"].sum())
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def al_long_lines(torch_cuda):
+    """Al-like at N = 132: lines of 528 energies (float line copy)."""
+    w = workload("al_fcc_100", 132)
+    N = 132
+    s = make_system(w.system)
+    mu = s.mu_centroid
+
+    def window(eps):
+        return mu + w.window[0], mu + w.window[1]
+
+    c = _subset_case("al_fcc", N, w.eta, w.temps, window, 0, -1, 5, 1649302 + 11)
+    r = Oracle(c["s"]).rates(N, c["eps"], c["evec"], c["om"], c["u"], c["sk"], c["sn"], mu, w.temps, w.eta)
+    c.update(N=N, mu=mu, w=w, r=r)
+    return c
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_al_like_long_line_reduced(al_long_lines, prec):
+    from paper_2306_16493_amd import Context
+    c = al_long_lines
+    w, N = c["w"], c["N"]
+    ctx = Context(c["s"])
+    p = ctx.params(N, c["mu"], w.temps, w.eta, c["lo"], c["hi"], precision=prec, k_subset=c["kpick"])
+    log(f"[instance] al_fcc N={N} {prec}, {len(c['kpick'])} k points")
+    g = gpu_run(ctx, p)
+    assert np.array_equal(g["state_k"], c["sk"]) and np.array_equal(g["state_n"], c["sn"])
+    compare_rates(g, c["r"]["inv_tau"], c["eps"], c["sk"], c["sn"], tol=TOL_RED)
+    assert g["counts"]["n_terms"] == int(c["r"]["n_terms"].sum())
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,N,prec", [("box5_w4", 6, "fp64"), ("box5_w4", 5, "fp32"),
+                                         ("box446_w2a2", 6, "fp64"), ("box446_w2a2", 5, "fp32")])
+def test_workgroup_kernel_boxes(torch_cuda, name, N, prec):
+    """Rp boxes the wave kernel does not serve (5^3, 4 x 4 x 6) take the
+    workgroup form of the rate kernel."""
+    from paper_2306_16493_amd import Context
+    s = make_system(name)
+    eta, temps = 0.05, [300.0, 600.0]
+    mu = s.mu_centroid
+    ctx = Context(s)
+    p = ctx.params(N, mu, temps, eta, -1e3, 1e3, precision=prec)
+    g = gpu_run(ctx, p)
+    r = Oracle(s).run(N, mu, temps, eta, -1e3, 1e3)
+    log(f"[workgroup] {name} N={N} {prec}: {len(r['state_k'])} states")
+    assert np.array_equal(g["state_k"], r["state_k"]) and np.array_equal(g["state_n"], r["state_n"])
+    tol = TOL if prec == "fp64" else TOL_RED
+    compare_rates(g, r["inv_tau"], r["tables"][0], r["state_k"], r["state_n"], tol=tol)
+    cnt = g["counts"]
+    assert cnt["n_kq"] == r["n_kq"] and cnt["n_terms"] == int(r["n_terms"].sum())
+    res = g["res"]
+    sig = ctx.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, temps, N ** 3)
+    assert rel_err(sig, r["sigma"]) < tol
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["degen_w4", "degen_w4_sym"])
+def test_degenerate_bands_and_modes(torch_cuda, name):
+    """Every band 2-fold and every phonon 3-fold (H = h (x) I_2, isotropic
+    springs).  With a random vertex only the sums over each degenerate group
+    of 1/tau are gauge-invariant and are compared; with g = g' (x) I_2 every
+    per-state rate and sigma are gauge-invariant and compared per state."""
+    from paper_2306_16493_amd import Context
+    s = make_system(name)
+    N, eta, temps = 6, 0.05, [300.0]
+    mu = s.mu_centroid
+    ctx = Context(s)
+    p = ctx.params(N, mu, temps, eta, -1e3, 1e3)
+    g = gpu_run(ctx, p)
+    r = Oracle(s).run(N, mu, temps, eta, -1e3, 1e3)
+    assert np.array_equal(g["state_k"], r["state_k"]) and np.array_equal(g["state_n"], r["state_n"])
+    assert rel_err(g["energy"], r["energy"]) < TOL
+    # velocities: P dH/dk P is a multiple of the identity inside each pair,
+    # so they are gauge-invariant here
+    assert np.max(np.abs(g["vel"] - r["vel"])) <= TOL * np.abs(r["vel"]).max()
+    log(f"[degenerate] {name}: {len(r['state_k'])} states, all in 2-fold groups")
+    if name == "degen_w4":
+        compare_rates(g, r["inv_tau"], r["tables"][0], r["state_k"], r["state_n"])
+    else:
+        it_g, it_o = g["inv_tau"], r["inv_tau"]
+        err = np.abs(it_g - it_o) / np.maximum(np.abs(it_o), 1e-12 * np.abs(it_o).max())
+        log(f"  per-state max rel err 1/tau {err.max():.3e}")
+        assert err.max() < TOL
+        res = g["res"]
+        sig = ctx.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, temps, N ** 3)
+        assert rel_err(sig, r["sigma"]) < TOL
+    cnt = g["counts"]
+    assert cnt["n_excluded_modes"] == 3  # the acoustic triplet at Gamma
+    ctx.close()
+
+
+def test_state_batches_within_memory_budget(torch_cuda):
+    """mem_budget_bytes forces several state batches; the result is bitwise
+    the one-batch result, and matches the oracle.  Too small a budget gives
+    EPH_E_NOMEM."""
+    from paper_2306_16493_amd import Context, EphError
+    from paper_2306_16493_amd.eph import EPH_E_NOMEM
+    w = workload("toy_sc_8")
+    s = make_system(w.system)
+    ctx = Context(s)
+    p, (N, mu, lo, hi) = params_for(ctx, w, s)
+    ctx.set_profiling(True)
+    one = gpu_run(ctx, p)
+    assert ctx.stage_times()["xform_launches"] == 1
+    with pytest.raises(EphError) as ei:
+        gpu_run(ctx, ctx.params(N, mu, w.temps, w.eta, lo, hi, mem_budget_bytes=1))
+    assert ei.value.code == EPH_E_NOMEM
+    m = re.search(r"grid tables and lists \((\d+) bytes\)", str(ei.value))
+    assert m, str(ei.value)
+    with pytest.raises(EphError) as ei:
+        gpu_run(ctx, ctx.params(N, mu, w.temps, w.eta, lo, hi, mem_budget_bytes=int(m.group(1)) + 1))
+    assert ei.value.code == EPH_E_NOMEM
+    m = re.search(r"minimum of (\d+) bytes \((\d+) bytes of tables and lists plus (\d+) bytes per state",
+                  str(ei.value))
+    assert m, str(ei.value)
+    fixed, per_state = int(m.group(2)), int(m.group(3))
+    ns = one["counts"]["n_states"]
+    budget = fixed + per_state * ((ns + 3) // 4)
+    many = gpu_run(ctx, ctx.params(N, mu, w.temps, w.eta, lo, hi, mem_budget_bytes=budget))
+    nb = ctx.stage_times()["xform_launches"]
+    log(f"[budget] {ns} states: {nb} batches within {budget} bytes")
+    assert nb >= 4
+    assert np.array_equal(many["inv_tau"], one["inv_tau"])
+    assert many["counts"] == one["counts"]
+    r = Oracle(s).run(N, mu, w.temps, w.eta, lo, hi)
+    compare_rates(many, r["inv_tau"], r["tables"][0], r["state_k"], r["state_n"])
+    ctx.close()
+
+
+def test_line_limit_unsupported(torch_cuda):
+    """Lines longer than EPH_MAX_LINE energies are rejected before any work."""
+    from paper_2306_16493_amd import Context, EphError
+    from paper_2306_16493_amd.eph import EPH_E_UNSUPPORTED
+    s = make_system("mini_w8")
+    ctx = Context(s)
+    with pytest.raises(EphError) as ei:
+        ctx.count_states(ctx.params(257, s.mu_centroid, [300.0], 0.02, -1e3, 1e3))
+    assert ei.value.code == EPH_E_UNSUPPORTED
+    ctx.close()

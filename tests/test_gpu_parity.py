@@ -8,7 +8,7 @@ exact.
 import numpy as np
 import pytest
 
-from gpu_helpers import log, params_for, gpu_run, degenerate_mask, rel_err
+from gpu_helpers import log, params_for, gpu_run, compare_rates, rel_err
 from synth import make_system, workload
 from oracle import Oracle
 
@@ -23,24 +23,6 @@ def torch_cuda():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch
-
-
-def compare_rates(g, o_inv, eps_table, sk, sn, tol=TOL):
-    deg = degenerate_mask(eps_table, sk, sn)
-    it_g, it_o = g["inv_tau"], o_inv
-    scale = np.max(np.abs(it_o))
-    for t in range(it_o.shape[0]):
-        a, b = it_g[t][~deg], it_o[t][~deg]
-        err = np.abs(a - b) / np.maximum(np.abs(b), 1e-12 * scale)
-        log(f"  T{t}: max rel err 1/tau = {err.max() if err.size else 0:.3e} over {err.size} states "
-            f"({deg.sum()} near-degenerate)")
-        assert err.size == 0 or err.max() < tol
-        if deg.any():
-            # near-degenerate states: compare sums over the degenerate set at each k
-            for k in np.unique(sk[deg]):
-                sel = (sk == k) & deg
-                assert abs(it_g[t][sel].sum() - it_o[t][sel].sum()) <= tol * max(abs(it_o[t][sel].sum()),
-                                                                                 1e-12 * scale)
 
 
 def full_parity(torch, name, grid=None, temps=None, window=None, k_subset=None):

@@ -9,6 +9,7 @@ import math
 import numpy as np
 import pytest
 import scipy.constants as sc
+from scipy import integrate, special
 
 from synth import System, make_system, ws_block, lattice_block
 import oracle
@@ -203,6 +204,67 @@ def test_isotropic_springs_closed_form():
         nrm = np.linalg.norm(u[t], axis=1)
         assert np.allclose(nrm, np.sqrt(CPH / (2 * M * hw[t])), rtol=1e-12)
 
+
+
+def diatomic_chain(M1, M2, K, a=3.0):
+    """Simple-cubic cell with atoms at 0 and a/2 along x, isotropic springs
+    K (eV/A^2) between x-neighbours only: the x, y and z displacements each
+    form the textbook diatomic chain."""
+    I, z = np.eye(3), np.zeros((3, 3))
+    ifc = {(0, 0, 0): np.block([[2 * K * I, -K * I], [-K * I, 2 * K * I]]),
+           (1, 0, 0): np.block([[z, z], [-K * I, z]]),     # atom 2 at 0 <-> atom 1 at +a
+           (-1, 0, 0): np.block([[z, -K * I], [z, z]])}
+    return custom(np.diag([a, a, a]), [M1, M2], {(0, 0, 0): np.zeros((1, 1))}, 1, ifc, {},
+                  tau=np.array([[0.0, 0.0, 0.0], [a / 2, 0.0, 0.0]]))
+
+
+def test_diatomic_chain_unequal_masses_closed_form():
+    """Dynamical matrix with the mass scaling 1/sqrt(M M') (Sec. II.B): for
+    the diatomic chain, lambda = K(1/M1 + 1/M2) +- K sqrt((1/M1 + 1/M2)^2 -
+    4 sin^2(theta/2)/(M1 M2)), theta = 2 pi q1, each 3-fold; hbar w =
+    sqrt(C lambda).  Unequal masses make a slip such as sqrt(M M') -> M fail."""
+    M1, M2, K = 26.98, 69.72, 1.3
+    o = Oracle(diatomic_chain(M1, M2, K))
+    N = 6
+    om, u, lam = o.phonons(N)
+    th = 2 * math.pi * bf.grid_points(N)[:, 0] / N
+    s = 1 / M1 + 1 / M2
+    root = np.sqrt(np.maximum(s * s - 4 * np.sin(th / 2) ** 2 / (M1 * M2), 0.0))
+    ref = np.sort(np.repeat(np.stack([K * (s - root), K * (s + root)], 1), 3, axis=1), axis=1)
+    assert np.max(np.abs(lam - ref)) < 1e-13 * ref.max()
+    assert np.max(np.abs(om - np.sqrt(CPH * np.maximum(ref, 0.0)))) < 1e-13 * om.max()
+
+
+def test_displacements_mass_weighted_norm_and_eigenvectors():
+    """Mode displacements u = e (hbar / 2 M_mu w)^(1/2) (Sec. II.B) with
+    unequal masses: sum_mu M_mu |u_mu nu|^2 = C / (2 hbar w_nu) for every
+    kept mode, and e = u sqrt(2 M_mu hbar w / C) is an eigenvector of the
+    mass-scaled dynamical matrix of the chain, written out here:
+    D11 = 2K/M1, D22 = 2K/M2, D12 = -K (1 + e^{-i theta}) / sqrt(M1 M2)."""
+    M1, M2, K = 26.98, 69.72, 1.3
+    o = Oracle(diatomic_chain(M1, M2, K))
+    N = 6
+    om, u, lam = o.phonons(N, omega_cut=1e-4)
+    mass = np.repeat([M1, M2], 3)
+    kept = om >= 1e-4
+    # the springs act along x only, so the acoustic branch vanishes on the whole q1 = 0 plane
+    assert kept.sum() == 6 * N ** 3 - 3 * N ** 2
+    norm = np.einsum("qnm,m->qn", np.abs(u) ** 2, mass)
+    ref = CPH / (2 * np.where(kept, om, 1.0))
+    assert np.max(np.abs(norm - ref)[kept] / ref[kept]) < 1e-13
+    assert np.all(np.abs(u[~kept]) == 0)
+    th = 2 * math.pi * bf.grid_points(N)[:, 0] / N
+    for q in range(N ** 3):
+        d12 = -K * (1 + np.exp(-1j * th[q])) / math.sqrt(M1 * M2)
+        D = np.zeros((6, 6), complex)
+        D[:3, :3] = np.eye(3) * 2 * K / M1
+        D[3:, 3:] = np.eye(3) * 2 * K / M2
+        D[:3, 3:] = np.eye(3) * d12
+        D[3:, :3] = np.eye(3) * np.conj(d12)
+        for nu in np.nonzero(kept[q])[0]:
+            e = u[q, nu] * np.sqrt(2 * mass * om[q, nu] / CPH)
+            assert abs(np.linalg.norm(e) - 1) < 1e-12
+            assert np.max(np.abs(D @ e - lam[q, nu] * e)) < 1e-12 * np.abs(D).max()
 
 # ---------------------------------------------------------------- P4
 def test_single_vertex_term_phase_free():
@@ -488,3 +550,47 @@ def test_wiedemann_franz_degenerate_limit():
     sig, _, kap = o.transport(eps[:, 0], vel[:, 0], inv, -1.5, [T], N ** 3)
     lorenz = kap[0, 0, 0] / (sig[0, 0, 0] * T)
     assert lorenz == pytest.approx(math.pi ** 2 / 3 * (sc.k / sc.e) ** 2, rel=0.03)
+
+
+def _square_lattice_dos(e, t):
+    """DOS of 2t(cos a + cos b) for a, b uniform, normalised to 1:
+    K(1 - (e/4t)^2) / (2 pi^2 |t|) inside the band (complete elliptic
+    integral of the first kind, parameter m = k^2)."""
+    m = 1.0 - (e / (4 * t)) ** 2
+    return special.ellipk(m) / (2 * math.pi ** 2 * abs(t)) if m > 0 else 0.0
+
+
+def _transport_function_cosine_band(E, t):
+    """Xi(E) = <sin^2 theta_x delta(E - 2t sum_i cos theta_i)>, up to a
+    constant: the x integral of sin^2 times the 2-D DOS of the y, z part,
+    by adaptive quadrature with break points where the 2-D DOS is singular
+    (e = 0) or steps (e = +-4|t|)."""
+    pts = []
+    for e0 in (0.0, 4 * abs(t), -4 * abs(t)):
+        c = (E - e0) / (2 * t)
+        if abs(c) < 1:
+            a = math.acos(c)
+            pts += [a, 2 * math.pi - a]
+    f = lambda th: math.sin(th) ** 2 * _square_lattice_dos(E - 2 * t * math.cos(th), t)
+    v, _ = integrate.quad(f, 0, 2 * math.pi, points=sorted(pts), limit=400, epsabs=0, epsrel=1e-11)
+    return v
+
+
+def test_seebeck_magnitude_mott_formula():
+    """Seebeck coefficient (Sec. II.C) in the degenerate limit: with constant
+    tau, S = -(pi^2/3) k_B^2 T d ln Xi(E)/dE at E = mu (Mott), with Xi the
+    transport function of the NN cosine band computed above from the 2-D
+    DOS in closed form, independently of the oracle.  Corrections are of
+    relative order (k_B T / t)^2 and from the finite grid; measured 0.3%."""
+    t, mu, T, N = -1.0, -4.0, 1000.0, 64
+    assert abs(integrate.quad(lambda e: _square_lattice_dos(e, t), -4, 4, points=[0], limit=400)[0] - 1) < 1e-9
+    o = Oracle(nn_band(0.0, t))
+    eps, _, vel = o.electrons(N)
+    inv = np.full((1, N ** 3), 1e13)
+    _, see, _ = o.transport(eps[:, 0], vel[:, 0], inv, mu, [T], N ** 3)
+    h = 1e-3
+    dlog = (math.log(_transport_function_cosine_band(mu + h, t)) -
+            math.log(_transport_function_cosine_band(mu - h, t))) / (2 * h)
+    mott = -(math.pi ** 2 / 3) * KB ** 2 * T * dlog
+    assert see[0, 0, 0] == pytest.approx(mott, rel=0.02)
+    assert see[0, 1, 1] == pytest.approx(see[0, 0, 0], rel=1e-10)
