@@ -204,6 +204,22 @@ int32_t eph_conductivity(eph_ctx *ctx, int64_t n_states, const double *energy_eV
                          int32_t n_temps, const double *temps_K, int64_t n_kpoints,
                          void *stream, double *sigma_S_per_m);
 
+/* eph_conductivity for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels and the same bit-identical
+ * result, but the reduction's workspace is a static device array of
+ * 9,328 doubles (74,624 bytes) per GPU, set up by eph_load_wannier and held
+ * until the process ends; the call itself allocates nothing.  The workspace
+ * does not grow with n_states, so the only size limit is n_temps <=
+ * EPH_MAX_TEMPS (EPH_E_INVALID beyond it).  Every call on one GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (several host
+ * threads or streams) race and must be serialised by the caller.
+ * EPH_E_STATE if the context has no workspace address. */
+int32_t eph_conductivity_noalloc(eph_ctx *ctx, int64_t n_states, const double *energy_eV,
+                                 const double *vel_ms, const double *inv_tau_s, double mu_eV,
+                                 int32_t n_temps, const double *temps_K, int64_t n_kpoints,
+                                 void *stream, double *sigma_S_per_m);
+
 /* Transport coefficients (Sec. II.C, the coefficients built from the same
  * relaxation-time sums as sigma).  With energies in eV and
  *   M_n,ab(T) = 2 e^2/(n_kpoints V) sum_s v_a v_b tau_s f(1-f)/(k_B T)

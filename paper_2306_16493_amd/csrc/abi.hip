@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 
 #include "internal.h"
@@ -41,6 +42,8 @@ hipError_t DevBuf::ensure(size_t n) {
 }  // namespace eph
 
 using namespace eph;
+
+static hipError_t scratch_address(int device, double **out);
 
 namespace {
 
@@ -248,6 +251,10 @@ int32_t eph_load_wannier(const eph_model *m, int32_t device, eph_ctx **out) {
   if (device < 0 || device >= ndev) return bad(EPH_E_INVALID, "device index out of range");
   DeviceGuard dg(device);
   if (!dg.ok) return bad(EPH_E_DEVICE, "hipSetDevice failed");
+  {  // the static workspace of eph_conductivity_noalloc on this device
+    hipError_t e = scratch_address(device, &c->scratch);
+    if (e != hipSuccess) return bad(EPH_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
 
   c->device = device;
   c->nw = nw;
@@ -632,11 +639,66 @@ int32_t eph_stage_times(const eph_ctx *c, double *ms, int64_t *launches) {
 }  // extern "C"
 
 namespace {
+// Workspace of the conductivity reduction, in doubles: per-block partials
+// [kSigBlocks][EPH_MAX_TEMPS * 9], the reduced moments [3][EPH_MAX_TEMPS * 9]
+// and k_B T [EPH_MAX_TEMPS].
+constexpr int kSigBlocks = 256;
+constexpr size_t kSigWorkDoubles = (size_t)kSigBlocks * EPH_MAX_TEMPS * 9 + 3 * EPH_MAX_TEMPS * 9 + EPH_MAX_TEMPS;
+
+// Static device workspace of eph_conductivity_noalloc: one copy per GPU,
+// held until the process ends.  In host code `scratch` only names the
+// symbol; its device address comes from hipGetSymbolAddress (per device).
+static __device__ __align__(256) double scratch[kSigWorkDoubles];
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64] = {nullptr};
+
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the caller has made `device` current).
+static hipError_t scratch_address(int device, double **out) {
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+namespace {
+
 // Moments 0..n_orders-1 of the SERTA sum on the device inputs, into host
-// out[order][EPH_MAX_TEMPS * 9] (S/m times eV^order).
+// out[order][EPH_MAX_TEMPS * 9] (S/m times eV^order).  work is a device
+// buffer of kSigWorkDoubles; every part of it is written before it is read.
 int32_t moments(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
                 const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K, int64_t n_kpoints,
-                void *stream, int n_orders, double (*out)[EPH_MAX_TEMPS * 9]) {
+                void *stream, int n_orders, double (*out)[EPH_MAX_TEMPS * 9], double *work) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Units U = units();
+  double *part = work;
+  double *outd = part + (size_t)kSigBlocks * EPH_MAX_TEMPS * 9;
+  double *kts = outd + 3 * EPH_MAX_TEMPS * 9;
+  double hk[EPH_MAX_TEMPS] = {1.0, 1.0, 1.0, 1.0};
+  for (int t = 0; t < n_temps; t++) hk[t] = U.kb_evk * temps_K[t];
+  EPH_HIP(c, hipMemcpyAsync(kts, hk, sizeof(hk), hipMemcpyHostToDevice, st));
+  const double pref = 2.0 * kCharge / ((double)n_kpoints * c->volume * 1e-30);
+  for (int o = 0; o < n_orders; o++)
+    EPH_HIP(c, launch_sigma(n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, kts, pref, part, kSigBlocks,
+                            outd + o * EPH_MAX_TEMPS * 9, st, o));
+  EPH_HIP(c, hipMemcpyAsync(out, outd, sizeof(double) * n_orders * EPH_MAX_TEMPS * 9, hipMemcpyDeviceToHost, st));
+  EPH_HIP(c, hipStreamSynchronize(st));
+  return EPH_OK;
+}
+
+// Argument checks shared by the conductivity and transport entry points.
+int32_t check_moment_args(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
+                          const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K,
+                          int64_t n_kpoints) {
   if (!c) return EPH_E_INVALID;
   c->err.clear();
   if (n_states < 0) return fail(c, EPH_E_INVALID, "n_states < 0");
@@ -646,27 +708,20 @@ int32_t moments(eph_ctx *c, int64_t n_states, const double *energy_eV, const dou
   if (n_kpoints < 1) return fail(c, EPH_E_INVALID, "n_kpoints must be >= 1");
   if (n_states > 0 && (!energy_eV || !vel_ms || !inv_tau_s)) return fail(c, EPH_E_INVALID, "NULL input buffer");
   if (!std::isfinite(mu_eV)) return fail(c, EPH_E_INVALID, "mu must be finite");
+  return EPH_OK;
+}
+
+// moments() on the context's grow-only workspace (allocated on first use).
+int32_t moments_ctx(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
+                    const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K, int64_t n_kpoints,
+                    void *stream, int n_orders, double (*out)[EPH_MAX_TEMPS * 9]) {
+  int32_t r = check_moment_args(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints);
+  if (r != EPH_OK) return r;
   DeviceGuard dg(c->device);
   if (!dg.ok) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const Units U = units();
-  const int nblk = 256;
-  // partials [nblk][36], then out [3][36], then kts [4]
-  EPH_HIP(c, c->sig_part.ensure(sizeof(double) *
-                                ((size_t)nblk * EPH_MAX_TEMPS * 9 + 3 * EPH_MAX_TEMPS * 9 + EPH_MAX_TEMPS)));
-  double *part = c->sig_part.as<double>();
-  double *outd = part + (size_t)nblk * EPH_MAX_TEMPS * 9;
-  double *kts = outd + 3 * EPH_MAX_TEMPS * 9;
-  double hk[EPH_MAX_TEMPS] = {1.0, 1.0, 1.0, 1.0};
-  for (int t = 0; t < n_temps; t++) hk[t] = U.kb_evk * temps_K[t];
-  EPH_HIP(c, hipMemcpyAsync(kts, hk, sizeof(hk), hipMemcpyHostToDevice, st));
-  const double pref = 2.0 * kCharge / ((double)n_kpoints * c->volume * 1e-30);
-  for (int o = 0; o < n_orders; o++)
-    EPH_HIP(c, launch_sigma(n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, kts, pref, part, nblk,
-                            outd + o * EPH_MAX_TEMPS * 9, st, o));
-  EPH_HIP(c, hipMemcpyAsync(out, outd, sizeof(double) * n_orders * EPH_MAX_TEMPS * 9, hipMemcpyDeviceToHost, st));
-  EPH_HIP(c, hipStreamSynchronize(st));
-  return EPH_OK;
+  EPH_HIP(c, c->sig_part.ensure(sizeof(double) * kSigWorkDoubles));
+  return moments(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints, stream, n_orders,
+                 out, c->sig_part.as<double>());
 }
 
 void inv3(const double *a, double *r) {
@@ -695,7 +750,24 @@ int32_t eph_conductivity(eph_ctx *c, int64_t n_states, const double *energy_eV, 
                          int64_t n_kpoints, void *stream, double *sigma_S_per_m) {
   if (c && !sigma_S_per_m) return fail(c, EPH_E_INVALID, "sigma output is NULL");
   double m[1][EPH_MAX_TEMPS * 9];
-  const int32_t r = moments(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints, stream, 1, m);
+  const int32_t r = moments_ctx(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints, stream, 1, m);
+  if (r != EPH_OK) return r;
+  for (int t = 0; t < n_temps; t++)
+    for (int q = 0; q < 9; q++) sigma_S_per_m[t * 9 + q] = m[0][t * 9 + q];
+  return EPH_OK;
+}
+
+int32_t eph_conductivity_noalloc(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
+                                 const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K,
+                                 int64_t n_kpoints, void *stream, double *sigma_S_per_m) {
+  int32_t r = check_moment_args(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints);
+  if (r != EPH_OK) return r;
+  if (!sigma_S_per_m) return fail(c, EPH_E_INVALID, "sigma output is NULL");
+  if (!c->scratch) return fail(c, EPH_E_STATE, "no static workspace on this context's device");
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  double m[1][EPH_MAX_TEMPS * 9];
+  r = moments(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints, stream, 1, m, c->scratch);
   if (r != EPH_OK) return r;
   for (int t = 0; t < n_temps; t++)
     for (int q = 0; q < 9; q++) sigma_S_per_m[t * 9 + q] = m[0][t * 9 + q];
@@ -709,7 +781,7 @@ int32_t eph_transport(eph_ctx *c, int64_t n_states, const double *energy_eV, con
   if (c && (!sigma_S_per_m || !seebeck_V_per_K || !kappa_W_per_mK))
     return fail(c, EPH_E_INVALID, "NULL output");
   double m[3][EPH_MAX_TEMPS * 9];
-  const int32_t r = moments(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints, stream, 3, m);
+  const int32_t r = moments_ctx(c, n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, temps_K, n_kpoints, stream, 3, m);
   if (r != EPH_OK) return r;
   for (int t = 0; t < n_temps; t++) {
     const double *m0 = m[0] + t * 9, *m1 = m[1] + t * 9, *m2 = m[2] + t * 9;

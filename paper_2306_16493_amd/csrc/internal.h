@@ -90,6 +90,7 @@ struct eph_ctx {
   eph::DevBuf xbuf;                     // X_s = Re transform + j rotation
   eph::DevBuf counters;                 // int64 counters
   eph::DevBuf sig_part;                 // sigma partial sums
+  double *scratch = nullptr;            // device address of the static workspace (eph_conductivity_noalloc)
   eph::DevBuf state_cnt;                // per-state int64 counts
   eph::DevBuf occ;                      // Fermi and Bose factor tables
   // stage timing

@@ -24,7 +24,7 @@ MAX_TEMPS = 4
 
 # every symbol declared in include/eph.h
 EXPORTS = ("eph_load_wannier", "eph_free", "eph_last_error", "eph_scattering_rates", "eph_select_states",
-           "eph_conductivity", "eph_transport", "eph_carrier_density", "eph_mobility",
+           "eph_conductivity", "eph_conductivity_noalloc", "eph_transport", "eph_carrier_density", "eph_mobility",
            "eph_set_profiling", "eph_stage_times", "eph_mlp_create", "eph_mlp_free", "eph_mlp_params",
            "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient", "eph_mlp_predict", "eph_mlp_blend",
            "eph_merge_rates")
@@ -87,6 +87,8 @@ def lib():
         L.eph_conductivity.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                        C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.eph_conductivity.restype = C.c_int32
+        L.eph_conductivity_noalloc.argtypes = L.eph_conductivity.argtypes
+        L.eph_conductivity_noalloc.restype = C.c_int32
         L.eph_set_profiling.argtypes = [C.c_void_p, C.c_int32]
         L.eph_set_profiling.restype = C.c_int32
         L.eph_stage_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -265,11 +267,14 @@ class Context:
                                             C.byref(cnt)))
         return k[:ns], n[:ns], e[:ns], v[:ns]
 
-    def conductivity(self, energy, vel, inv_tau, mu, temps, n_kpoints, stream=None):
+    def conductivity(self, energy, vel, inv_tau, mu, temps, n_kpoints, stream=None, noalloc=False):
+        """sigma [nt][3][3] in S/m; noalloc=True calls eph_conductivity_noalloc
+        (static device workspace, no allocation in the call)."""
         temps = np.ascontiguousarray(np.atleast_1d(temps), np.float64)
         out = np.zeros((temps.shape[0], 3, 3))
         ns = int(energy.shape[0])
-        st = lib().eph_conductivity(self._h, ns, _dptr(energy.contiguous()), _dptr(vel.contiguous()),
+        fn = lib().eph_conductivity_noalloc if noalloc else lib().eph_conductivity
+        st = fn(self._h, ns, _dptr(energy.contiguous()), _dptr(vel.contiguous()),
                                     _dptr(inv_tau.contiguous()), float(mu), temps.shape[0], _ptr(temps),
                                     int(n_kpoints), C.c_void_p(stream) if stream else None, _ptr(out))
         self._check(st)
