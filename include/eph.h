@@ -237,6 +237,74 @@ int32_t eph_transport(eph_ctx *ctx, int64_t n_states, const double *energy_eV, c
                       int64_t n_kpoints, void *stream, double *sigma_S_per_m, double *seebeck_V_per_K,
                       double *kappa_W_per_mK);
 
+/* ------------------------------------------------------------------------
+ * Iterative solution of the linearised BTE (Sec. II.C, iteration equation;
+ * Sec. III.E, compressed storage).  The transition rates of a state
+ * s = (n,k) to a final state (m, k+q) are
+ *   Gamma_s(q,m) = (2 pi/hbar)(1/N^3) sum_nu |g_mn^nu(k,q)|^2
+ *                  [(N_qnu + f_m,k+q) delta(x+) + (1 + N_qnu - f_m,k+q) delta(x-)],
+ * the terms of 1/tau_s before they are summed over (q, m), so that
+ * sum_{q,m} Gamma_s(q,m) = 1/tau_s; they carry the same sieve and factors
+ * as the rates.  Only entries whose final state is itself a selected state
+ * are stored (any other final state is not part of the solution and carries
+ * F = 0).  Storage is by rows (CSR): row s holds, for each entry, the index
+ * of the final state in the state list (int32) and one FP64 value per
+ * temperature, values laid out [n_temps][nnz].  The iteration is
+ *   F^{i+1}_s = F0_s + tau_s sum_e Gamma_e F^i_{col_e},  F0 = v tau,
+ * and sigma after each iteration is
+ *   sigma_ab = 2 e^2/(n_kpoints V k_B T) sum_s v_a F_b f(1-f)
+ * (iteration 0 is the SERTA sigma of eph_conductivity).  States with
+ * 1/tau = 0 keep F = 0.  Available for FP64 on the Rp boxes served by the
+ * wave rate kernel (cubic, edge 4 or 6); EPH_E_UNSUPPORTED otherwise.
+ * ------------------------------------------------------------------------ */
+typedef struct eph_gamma eph_gamma;
+
+/* Memory estimate of the transition rates before they are computed (the
+ * preprocessing estimate of Sec. III.A): runs the state selection and the
+ * energy-conservation sieve only, and returns the number of stored entries
+ * (*nnz) and their bytes (*bytes = nnz (4 + 8 n_temps) + 8 (n_states + 1)).
+ * State outputs as eph_select_states (DEVICE buffers, capacity in states;
+ * EPH_E_TRUNCATED with capacity < n_states). */
+int32_t eph_gamma_estimate(eph_ctx *ctx, const eph_rates_params *params, int64_t capacity, int32_t *state_k,
+                           int32_t *state_n, double *energy_eV, double *vel_ms, int64_t *nnz, int64_t *bytes);
+
+/* eph_scattering_rates (same arguments and outputs) that also builds the
+ * transition rates into *gamma (free with eph_gamma_free).  A counting pass
+ * (the sieve only) sizes the rows first.  The rows stay in device memory
+ * when they fit mem_budget_bytes beside the call's other buffers (with
+ * mem_budget_bytes = 0: when they fit the free device memory with 1 GiB to
+ * spare); otherwise they are written batch by batch, through a device
+ * staging buffer, to pinned host memory (the host spill of Sec. III.E), and
+ * eph_bte_iterate streams them back.  The rows of a state follow the order
+ * in which the kernel evaluates its vertices, which is fixed, so repeated
+ * calls give identical rows.  EPH_E_NOMEM when neither fits. */
+int32_t eph_rates_gamma(eph_ctx *ctx, const eph_rates_params *params, int64_t capacity, int32_t *state_k,
+                        int32_t *state_n, double *energy_eV, double *vel_ms, double *inv_tau_s, eph_counts *counts,
+                        eph_gamma **gamma);
+
+/* Size and placement: states (rows), entries, temperatures, 1 if the rows
+ * are in pinned host memory, bytes.  Any output may be NULL. */
+int32_t eph_gamma_info(const eph_gamma *gamma, int64_t *n_states, int64_t *nnz, int32_t *n_temps, int32_t *on_host,
+                       int64_t *bytes);
+
+/* Copy the rows to HOST arrays (any may be NULL): row_start [n_states+1],
+ * col [nnz] (final-state index in the state list), val [n_temps][nnz] (1/s). */
+int32_t eph_gamma_copy(const eph_gamma *gamma, int64_t *row_start, int32_t *col, double *val);
+
+void eph_gamma_free(eph_gamma *gamma); /* NULL-safe */
+
+/* Iterate from F0 = v tau until the largest change of sigma is <= tol times
+ * its largest element, or max_iter iterations.  energy_eV [n_states],
+ * vel_ms [n_states][3] and inv_tau_s [n_temps][n_states] are the DEVICE
+ * outputs of the eph_rates_gamma call that built gamma (temperatures and mu
+ * are those of that call).  sigma_iter (HOST, [max_iter+1][n_temps][3][3])
+ * receives sigma after iterations 0..*n_iter; F_out (DEVICE
+ * [n_temps][n_states][3], may be NULL) the final mean free paths in m.  The
+ * iteration step is FP64 with a fixed summation order. */
+int32_t eph_bte_iterate(eph_ctx *ctx, const eph_gamma *gamma, const double *energy_eV, const double *vel_ms,
+                        const double *inv_tau_s, int64_t n_kpoints, int32_t max_iter, double tol, void *stream,
+                        double *sigma_iter, int32_t *n_iter, double *F_out);
+
 /* Carrier density for mobilities (Sec. II.C, mobility = sigma / (n e)):
  *   n(T) = 2/(N^3 V) sum_{all k of the N^3 grid} sum_{band_lo <= n <= band_hi} f(eps_nk)
  * in m^-3 into n_per_m3 [n_temps] (HOST).  The band energies are computed on

@@ -173,6 +173,52 @@ class Oracle:
                         _p(nte), _p(nkq))
         return dict(inv_tau=it, n_q_valid=nqv, n_terms=nte, n_kq=int(nkq[0]))
 
+    def gamma(self, N, eps, evec, omega, u, state_k, state_n, mu, temps, eta, sw=6.0, omega_cut=1e-4):
+        """Transition rates of the iterative BTE: row_start [ns+1], fin [nnz]
+        (final state p*nw + m), val [nnz][nt] (1/s), rows in state order."""
+        state_k = np.ascontiguousarray(state_k, np.int32)
+        state_n = np.ascontiguousarray(state_n, np.int32)
+        ns = state_k.shape[0]
+        temps = np.ascontiguousarray(temps, np.float64)
+        nt = temps.shape[0]
+        assert nt <= 8
+        eps = np.ascontiguousarray(eps, np.float64)
+        evec = np.ascontiguousarray(evec, np.complex128)
+        omega = np.ascontiguousarray(omega, np.float64)
+        u = np.ascontiguousarray(u, np.complex128)
+        rs = np.zeros(ns + 1, np.int64)
+        L = lib()
+        L.orc_gamma.restype = C.c_int64
+        args = lambda fin, val: (C.byref(self.model), _i64(N), _p(eps), _p(evec), _p(omega), _p(u), _i64(ns),
+                                 _p(state_k), _p(state_n), C.c_double(mu), C.c_int32(nt), _p(temps),
+                                 C.c_double(eta), C.c_double(sw), C.c_double(omega_cut), _p(rs), fin, val)
+        nnz = L.orc_gamma(*args(None, None))
+        fin = np.zeros(max(nnz, 1), np.int64)
+        val = np.zeros((max(nnz, 1), nt))
+        L.orc_gamma(*args(_p(fin), _p(val)))
+        return dict(row_start=rs, fin=fin[:nnz], val=val[:nnz])
+
+    def bte(self, N, state_k, state_n, energy, vel, inv_tau, gamma, mu, temps, nk_total, n_iter):
+        """Iterative BTE from the SERTA start F0 = v tau: sigma after every
+        iteration [n_iter+1][nt][3][3] and the final F [nt][ns][3]."""
+        state_k = np.ascontiguousarray(state_k, np.int32)
+        state_n = np.ascontiguousarray(state_n, np.int32)
+        energy = np.ascontiguousarray(energy, np.float64)
+        vel = np.ascontiguousarray(vel, np.float64)
+        inv_tau = np.ascontiguousarray(inv_tau, np.float64)
+        temps = np.ascontiguousarray(temps, np.float64)
+        ns, nt = state_k.shape[0], temps.shape[0]
+        rs = np.ascontiguousarray(gamma["row_start"], np.int64)
+        fin = np.ascontiguousarray(gamma["fin"], np.int64)
+        val = np.ascontiguousarray(gamma["val"], np.float64)
+        assert val.shape[1:] == (nt,)
+        sig = np.zeros((n_iter + 1, nt, 3, 3))
+        F = np.zeros((nt, ns, 3))
+        lib().orc_bte(_i64(N), C.c_int(self.nw), _i64(ns), _p(state_k), _p(state_n), _p(energy), _p(vel),
+                      _p(inv_tau), _p(rs), _p(fin), _p(val), C.c_double(mu), C.c_int32(nt), _p(temps),
+                      _i64(nk_total), C.c_double(self.volume), C.c_int32(n_iter), _p(sig), _p(F))
+        return sig, F
+
     def sigma(self, energy, vel, inv_tau, mu, temps, nk_total):
         energy = np.ascontiguousarray(energy, np.float64)
         vel = np.ascontiguousarray(vel, np.float64)

@@ -25,6 +25,10 @@
  *   transport   sigma, Seebeck and electronic thermal conductivity from the
  *               (eps - mu)^n moments of the same sum (Sec. II.C);
  *               carrier density for mobilities.
+ *   iteration   transition rates Gamma_nm(k,k+q) (the terms of 1/tau before
+ *               the sum over final states) and the iterative solution
+ *               F^{i+1} = F^0 + tau sum Gamma F^i with sigma per iteration
+ *               (Sec. II.C iteration equation, Sec. III.E).
  * Loop order is the paper's CPU algorithm (Sec. III.A): outer loop over the
  * k points that carry states, inner loop over all q; OpenMP over k points.
  *
@@ -432,6 +436,190 @@ void orc_rates(const orc_model *md, int64_t N, const double *eps, const double *
   }
   free(gs);
   nkq[0] = total_kq;
+}
+
+/* ---------------------------------------------------------------------
+ * Transition rates of the iterative solution (Sec. II.C, the iteration
+ * equation; Sec. III.E stores their sum over modes and both phonon terms):
+ * for a state s = (n,k) and a final state (m, p = k+q) with a kept term,
+ *   Gamma_s(p,m)[t] = (2 pi/hbar)(1/N_q) sum_nu |g_mn^nu|^2
+ *                     [(N_qnu + f_mp) delta(x+) + (1 + N_qnu - f_mp) delta(x-)],
+ * the terms of 1/tau_s before they are summed over (q, m), so that
+ * sum_{q,m} Gamma_s(q,m) = 1/tau_s.  Same sieve, vertex and factors as
+ * orc_rates.  Entries are written state by state (rows in list order), q
+ * ascending, then m ascending: row_start[s] .. row_start[s+1]-1 hold
+ * fin[e] = p*nw + m and val[e*nt + t].  With fin == NULL only row_start is
+ * filled (entry counts, then the prefix sum); the return value is the number
+ * of entries.  States must be sorted by k.
+ * -------------------------------------------------------------------*/
+static int64_t gamma_state_terms(const orc_model *md, int64_t N, const double *eps, const double *omega,
+                                 int64_t kidx, int n, double eta, double sw, double omega_cut) {
+  /* number of (q, m) with at least one kept (nu, sign) term */
+  const int nw = md->nw, nm = 3 * md->na;
+  const int64_t NQ = N * N * N;
+  int64_t k[3], q[3], p[3], cnt = 0;
+  grid_coords(kidx, N, k);
+  const double en = eps[kidx * nw + n];
+  for (int64_t qi = 0; qi < NQ; qi++) {
+    grid_coords(qi, N, q);
+    for (int a = 0; a < 3; a++) p[a] = k[a] + q[a];
+    const int64_t pidx = grid_index(p, N);
+    for (int m = 0; m < nw; m++) {
+      int kept = 0;
+      for (int nu = 0; nu < nm && !kept; nu++) {
+        const double w = omega[qi * nm + nu];
+        if (w < omega_cut) continue;
+        if (fabs(en + w - eps[pidx * nw + m]) <= sw * eta || fabs(en - w - eps[pidx * nw + m]) <= sw * eta) kept = 1;
+      }
+      cnt += kept;
+    }
+  }
+  return cnt;
+}
+
+int64_t orc_gamma(const orc_model *md, int64_t N, const double *eps, const double *evec, const double *omega,
+                  const double *u, int64_t ns, const int32_t *state_k, const int32_t *state_n, double mu, int32_t nt,
+                  const double *temps, double eta, double sw, double omega_cut, int64_t *row_start, int64_t *fin,
+                  double *val) {
+  const int nw = md->nw, nm = 3 * md->na;
+  const int64_t NQ = N * N * N;
+  const double pref = 2.0 * ORC_PI / orc_hbar_evs() / (double)NQ;
+  const double kb = orc_kb_evk();
+  if (!fin) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < ns; s++)
+      row_start[s + 1] = gamma_state_terms(md, N, eps, omega, state_k[s], state_n[s], eta, sw, omega_cut);
+    row_start[0] = 0;
+    for (int64_t s = 0; s < ns; s++) row_start[s + 1] += row_start[s];
+    return row_start[ns];
+  }
+  int64_t ng = 0;
+  int64_t *gs = malloc(sizeof(int64_t) * (ns + 1));
+  for (int64_t s = 0; s < ns; s++)
+    if (s == 0 || state_k[s] != state_k[s - 1]) gs[ng++] = s;
+  gs[ng] = ns;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t gi = 0; gi < ng; gi++) {
+    const int64_t s0 = gs[gi], s1 = gs[gi + 1];
+    const int64_t kidx = state_k[s0];
+    int64_t k[3];
+    grid_coords(kidx, N, k);
+    cplx *Gk = malloc(sizeof(cplx) * (size_t)md->nrp * nm * nw * nw);
+    cplx *Gq = malloc(sizeof(cplx) * (size_t)nm * nw * nw);
+    int64_t *cur = malloc(sizeof(int64_t) * (s1 - s0));
+    for (int64_t s = s0; s < s1; s++) cur[s - s0] = row_start[s];
+    re_sum(md, N, k, Gk);
+    for (int64_t qi = 0; qi < NQ; qi++) {
+      int64_t q[3], p[3];
+      grid_coords(qi, N, q);
+      for (int a = 0; a < 3; a++) p[a] = k[a] + q[a];
+      const int64_t pidx = grid_index(p, N);
+      const double *ep = eps + pidx * nw, *wq = omega + qi * nm;
+      int gq_done = 0;
+      for (int64_t s = s0; s < s1; s++) {
+        const int n = state_n[s];
+        const double en = eps[kidx * nw + n];
+        for (int m = 0; m < nw; m++) {
+          int any = 0;
+          double acc[8] = {0};
+          for (int nu = 0; nu < nm; nu++) {
+            if (wq[nu] < omega_cut) continue;
+            double xp = en + wq[nu] - ep[m], xm = en - wq[nu] - ep[m];
+            int kp = fabs(xp) <= sw * eta, km = fabs(xm) <= sw * eta;
+            if (!kp && !km) continue;
+            if (!gq_done) {
+              rp_sum(md, N, q, Gk, Gq);
+              gq_done = 1;
+            }
+            any = 1;
+            cplx g = rotate(nw, nm, Gq, evec + (size_t)pidx * nw * nw * 2, evec + (size_t)kidx * nw * nw * 2,
+                            u + (size_t)qi * nm * nm * 2, m, n, nu);
+            double g2 = creal(g) * creal(g) + cimag(g) * cimag(g);
+            for (int t = 0; t < nt; t++) {
+              double kt = kb * temps[t];
+              double Nq = bose(wq[nu], kt), f = fermi(ep[m], mu, kt);
+              double a = 0.0;
+              if (kp) a += (Nq + f) * orc_delta(xp, eta);
+              if (km) a += (1.0 + Nq - f) * orc_delta(xm, eta);
+              acc[t] += pref * g2 * a;
+            }
+          }
+          if (!any) continue;
+          const int64_t e = cur[s - s0]++;
+          fin[e] = pidx * nw + m;
+          for (int t = 0; t < nt; t++) val[e * nt + t] = acc[t];
+        }
+      }
+    }
+    free(Gk);
+    free(Gq);
+    free(cur);
+  }
+  free(gs);
+  return row_start[ns];
+}
+
+/* ---------------------------------------------------------------------
+ * Iterative solution of the linearised BTE (Sec. II.C): with the mean free
+ * paths F0_s = v_s tau_s,
+ *   F^{i+1}_s = F0_s + tau_s sum_e Gamma_e F^i_{state(fin_e)},
+ * where final states that are not in the state list carry F = 0.  States
+ * with 1/tau = 0 are left out (F = 0).  sigma after every iteration (i = 0
+ * is the SERTA value):
+ *   sigma_ab = 2 e^2/(N_k V k_B T) sum_s v_a F_b f(1-f)
+ * into sigma[(n_iter+1)][nt][9]; the final F into F[nt][ns][3].  Rows and
+ * entries as written by orc_gamma (val[e*nt + t]).  Plain left-to-right sums.
+ * -------------------------------------------------------------------*/
+void orc_bte(int64_t N, int nw, int64_t ns, const int32_t *state_k, const int32_t *state_n, const double *energy,
+             const double *vel, const double *inv_tau, const int64_t *row_start, const int64_t *fin,
+             const double *val, double mu, int32_t nt, const double *temps, int64_t nk_total, double volume_a3,
+             int32_t n_iter, double *sigma, double *F) {
+  const int64_t NQ = N * N * N;
+  const double kb = orc_kb_evk();
+  const double vol = volume_a3 * 1e-30;
+  int64_t *sidx = malloc(sizeof(int64_t) * NQ * nw);
+  for (int64_t i = 0; i < NQ * nw; i++) sidx[i] = -1;
+  for (int64_t s = 0; s < ns; s++) sidx[(int64_t)state_k[s] * nw + state_n[s]] = s;
+  double *F0 = malloc(sizeof(double) * ns * 3), *Fo = malloc(sizeof(double) * ns * 3);
+  for (int t = 0; t < nt; t++) {
+    const double kt = kb * temps[t];
+    for (int64_t s = 0; s < ns; s++) {
+      const double it = inv_tau[t * ns + s];
+      for (int a = 0; a < 3; a++) F0[s * 3 + a] = it == 0.0 ? 0.0 : vel[s * 3 + a] / it;
+    }
+    memcpy(Fo, F0, sizeof(double) * ns * 3);
+    double *Fn = F + (size_t)t * ns * 3;
+    for (int32_t i = 0; i <= n_iter; i++) {
+      if (i > 0) {
+        for (int64_t s = 0; s < ns; s++) {
+          const double it = inv_tau[t * ns + s];
+          double acc[3] = {0.0, 0.0, 0.0};
+          if (it != 0.0)
+            for (int64_t e = row_start[s]; e < row_start[s + 1]; e++) {
+              const int64_t j = sidx[fin[e]];
+              if (j < 0) continue;
+              for (int a = 0; a < 3; a++) acc[a] += val[e * nt + t] * Fo[j * 3 + a];
+            }
+          for (int a = 0; a < 3; a++) Fn[s * 3 + a] = it == 0.0 ? 0.0 : F0[s * 3 + a] + acc[a] / it;
+        }
+        memcpy(Fo, Fn, sizeof(double) * ns * 3);
+      } else {
+        memcpy(Fn, F0, sizeof(double) * ns * 3);
+      }
+      double acc[9] = {0};
+      for (int64_t s = 0; s < ns; s++) {
+        if (inv_tau[t * ns + s] == 0.0) continue;
+        const double f = fermi(energy[s], mu, kt);
+        const double w = f * (1.0 - f) / kt;
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) acc[a * 3 + b] += vel[s * 3 + a] * Fo[s * 3 + b] * w;
+      }
+      for (int e = 0; e < 9; e++) sigma[((size_t)i * nt + t) * 9 + e] = 2.0 * ORC_E / ((double)nk_total * vol) * acc[e];
+    }
+  }
+  free(sidx);
+  free(F0);
+  free(Fo);
 }
 
 /* ---------------------------------------------------------------------

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 
@@ -40,6 +41,11 @@ hipError_t DevBuf::ensure(size_t n) {
 }
 
 }  // namespace eph
+
+eph_gamma::~eph_gamma() {
+  if (h_col) (void)hipHostFree(h_col);
+  if (h_val) (void)hipHostFree(h_val);
+}
 
 using namespace eph;
 
@@ -106,7 +112,8 @@ struct Workspace {
   size_t per_state = 0;
 };
 
-Workspace plan_workspace(const eph_ctx *c, int N, int precision, int64_t nkl, int64_t ns, bool wave) {
+Workspace plan_workspace(const eph_ctx *c, int N, int precision, int64_t nkl, int64_t ns, bool wave,
+                         bool gamma = false) {
   const size_t NQ = (size_t)N * N * N, nw = c->nw, nm = c->nm;
   const bool red = precision != EPH_FP64;
   Workspace w;
@@ -128,6 +135,7 @@ Workspace plan_workspace(const eph_ctx *c, int N, int precision, int64_t nkl, in
   t += 8 * (size_t)nkl;                                             // k subset
   const size_t nsl = (size_t)ns + 1;
   t += 8 * (3 * nsl + 2 * (size_t)ns + scan_tmp_elems((int64_t)nsl));  // groups, per-state counts
+  if (gamma) t += NQ * nw * 4 + 16 * nsl;                           // state index table, counts, row starts
   w.fixed = t;
   w.per_state = (size_t)c->box.count() * nm * nw * (red ? 8 : 16);  // X row
   return w;
@@ -315,9 +323,18 @@ int32_t eph_load_wannier(const eph_model *m, int32_t device, eph_ctx **out) {
   return EPH_OK;
 }
 
+// Transition rates requested from a rates call: count them only (memory
+// estimate), or build them.
+struct GammaReq {
+  bool estimate_only = false;
+  int64_t nnz = 0;
+  int64_t bytes = 0;
+  eph_gamma *out = nullptr;
+};
+
 static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
                           int32_t *state_n, double *energy_eV, double *vel_ms, double *inv_tau_s,
-                          eph_counts *counts, bool states_only) {
+                          eph_counts *counts, bool states_only, GammaReq *gr = nullptr) {
   if (!c) return EPH_E_INVALID;
   c->err.clear();
   if (!p) return fail(c, EPH_E_INVALID, "params is NULL");
@@ -356,6 +373,9 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
   const int gwave = rates_wave_group(nw, nm, c->box, N, p->precision);
   if (gwave == 0 && rates_smem_bytes(p->precision, N, nw, nm, c->box) > 160 * 1024)
     return fail(c, EPH_E_UNSUPPORTED, "Rp box too large for the workgroup rate kernel at this grid");
+  if (gr && (gwave == 0 || p->precision != EPH_FP64))
+    return fail(c, EPH_E_UNSUPPORTED,
+                "transition rates need FP64 and the wave rate kernel (cubic Rp box of edge 4 or 6)");
   const int64_t nkl = p->k_subset ? (int64_t)klist.size() : (int64_t)N * N * N;
   {  // the grid tables and lists alone must fit the budget (states not known yet)
     const Workspace w0 = plan_workspace(c, N, p->precision, nkl, 0, gwave > 0);
@@ -439,7 +459,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
   }
   EPH_HIP(c, launch_write_states(nkl, d_klist, nw, c->eps.as<double>(), c->vel.as<double>(), blo, bhi, p->win_lo_eV,
                                  p->win_hi_eV, c->offs.as<int64_t>(), state_k, state_n, energy_eV, vel_ms, st));
-  if (states_only) {
+  if (states_only && !gr) {
     EPH_HIP(c, hipStreamSynchronize(st));
     if (counts) *counts = cn;
     return EPH_OK;
@@ -450,7 +470,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     // the wave-autonomous kernel where it applies, else the workgroup form
     const int gmax = gwave > 0 ? gwave : rates_group_max(nw, nm);
     // state batches: the per-batch buffers (X) within the budget
-    const Workspace ws = plan_workspace(c, N, p->precision, nkl, ns, gwave > 0);
+    const Workspace ws = plan_workspace(c, N, p->precision, nkl, ns, gwave > 0, gr != nullptr);
     int64_t max_states;
     if (p->mem_budget_bytes > 0) {
       const size_t need = ws.fixed + ws.per_state * (size_t)gmax;
@@ -544,10 +564,100 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     a.occ_f = c->occ.as<double>();
     a.occ_n = c->occ.as<double>() + (size_t)NQ * nw * EPH_MAX_TEMPS;
     const int ncol = c->box.count() * nm * nw;
+    // ---- transition rates: count pass, row starts, placement ----
+    std::unique_ptr<eph_gamma> gam;
+    std::vector<int64_t> hrow;
+    bool spill = false;
+    int64_t stage_cap = 0;
+    const int nt = p->n_temps;
+    if (gr) {
+      EPH_HIP(c, c->stidx.ensure(sizeof(int32_t) * NQ * nw));
+      EPH_HIP(c, launch_state_index(NQ, nw, ns, state_k, state_n, c->stidx.as<int32_t>(), st));
+      EPH_HIP(c, c->gcur.ensure(sizeof(int64_t) * (ns + 1)));
+      EPH_HIP(c, launch_zero(c->gcur.p, sizeof(int64_t) * (ns + 1), st));
+      a.stidx = c->stidx.as<int32_t>();
+      a.g_cursor = c->gcur.as<int64_t>();
+      a.ng = ng;
+      a.gstart = gstart;
+      a.s_base = 0;
+      a.X = nullptr;
+      for (int q3 = 0; q3 < N; q3++) {
+        a.q3_lo = q3;
+        a.q3_hi = q3 + 1;
+        a.q3_cur = q3;
+        EPH_HIP(c, launch_rates_wave(EPH_FP64, a, st, kCount));
+      }
+      gam.reset(new eph_gamma());
+      gam->ctx = c;
+      EPH_HIP(c, gam->row.ensure(sizeof(int64_t) * (ns + 1)));
+      EPH_HIP(c, c->scan_tmp.ensure(sizeof(int64_t) * scan_tmp_elems(ns + 1)));
+      EPH_HIP(c, launch_scan(ns + 1, c->gcur.as<int64_t>(), gam->row.as<int64_t>(), c->scan_tmp.as<int64_t>(), st));
+      hrow.resize(ns + 1);
+      EPH_HIP(c, hipMemcpyAsync(hrow.data(), gam->row.p, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
+      EPH_HIP(c, hipStreamSynchronize(st));
+      const int64_t gnnz = hrow[ns];
+      const size_t ebytes = 4 + 8 * (size_t)nt;  // one entry: column index and one value per temperature
+      const size_t gbytes = (size_t)gnnz * ebytes + 8 * (size_t)(ns + 1);
+      if (gr->estimate_only) {
+        gr->nnz = gnnz;
+        gr->bytes = (int64_t)gbytes;
+        if (counts) *counts = cn;
+        return EPH_OK;
+      }
+      // resident in device memory when it fits beside the other buffers,
+      // else in pinned host memory, written through a staging buffer
+      int64_t group_max = 0;  // most entries of one group
+      for (int64_t g = 0; g < ng; g++) group_max = std::max(group_max, hrow[hg[g + 1]] - hrow[hg[g]]);
+      if (p->mem_budget_bytes > 0) {
+        const size_t rest = (size_t)p->mem_budget_bytes - ws.fixed;  // >= per_state * gmax (checked above)
+        if (gbytes - 8 * (size_t)(ns + 1) + ws.per_state * (size_t)gmax <= rest) {
+          max_states = (int64_t)((rest - (gbytes - 8 * (size_t)(ns + 1))) / ws.per_state);
+        } else {
+          spill = true;
+          stage_cap = (int64_t)((rest - ws.per_state * (size_t)gmax) / 2 / ebytes);
+          if (stage_cap < std::max<int64_t>(group_max, 1))
+            return fail(c, EPH_E_NOMEM, "mem_budget_bytes leaves no room to stage the transition rates of one group (" +
+                                            std::to_string(group_max * ebytes) + " bytes)");
+          max_states = (int64_t)((rest - (size_t)stage_cap * ebytes) / ws.per_state);
+        }
+      } else {
+        size_t freeb = 0, totalb = 0;
+        EPH_HIP(c, hipMemGetInfo(&freeb, &totalb));
+        const size_t xb = std::min<size_t>((size_t)8 << 30, ws.per_state * (size_t)ns);
+        if (gbytes + xb + ((size_t)1 << 30) > freeb) {
+          spill = true;
+          stage_cap = std::max<int64_t>(group_max, std::min<int64_t>(gnnz, (int64_t)(((size_t)4 << 30) / ebytes)));
+        }
+      }
+      gam->ns = ns;
+      gam->nnz = gnnz;
+      gam->nt = nt;
+      for (int t = 0; t < nt; t++) gam->temps[t] = p->temps_K[t];
+      gam->mu = p->mu_eV;
+      gam->on_host = spill;
+      gam->stage_nnz = stage_cap;
+      if (spill) {
+        hipError_t e1 = hipHostMalloc((void **)&gam->h_col, sizeof(int32_t) * std::max<int64_t>(gnnz, 1));
+        hipError_t e2 = hipHostMalloc((void **)&gam->h_val, sizeof(double) * nt * std::max<int64_t>(gnnz, 1));
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+          (void)hipGetLastError();
+          return fail(c, EPH_E_NOMEM, "pinned host memory for the transition rates (" + std::to_string(gbytes) + " bytes)");
+        }
+        EPH_HIP(c, c->gstage_col.ensure(sizeof(int32_t) * stage_cap));
+        EPH_HIP(c, c->gstage_val.ensure(sizeof(double) * nt * stage_cap));
+      } else {
+        EPH_HIP(c, gam->col.ensure(sizeof(int32_t) * std::max<int64_t>(gnnz, 1)));
+        EPH_HIP(c, gam->val.ensure(sizeof(double) * nt * std::max<int64_t>(gnnz, 1)));
+      }
+      // every state's entries start at its row start
+      EPH_HIP(c, hipMemcpyAsync(c->gcur.p, gam->row.p, sizeof(int64_t) * ns, hipMemcpyDeviceToDevice, st));
+    }
     int64_t g0 = 0;
     while (g0 < ng) {
       int64_t g1 = g0 + 1;
-      while (g1 < ng && hg[g1 + 1] - hg[g0] <= max_states) g1++;
+      while (g1 < ng && hg[g1 + 1] - hg[g0] <= max_states &&
+             (!spill || hrow[hg[g1 + 1]] - hrow[hg[g0]] <= stage_cap))
+        g1++;
       const int64_t sa = hg[g0], sb = hg[g1];
       EPH_HIP(c, c->xbuf.ensure(xrow * (size_t)(sb - sa)));
       int eb0, eb1, eb2;
@@ -569,6 +679,12 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
       a.s_base = sa;
       a.X = c->xbuf.p;
       EPH_HIP(c, tm.mark(&eb1));
+      if (gr) {
+        a.g_base = spill ? hrow[sa] : 0;
+        a.g_col = spill ? c->gstage_col.as<int32_t>() : gam->col.as<int32_t>();
+        a.g_val = spill ? c->gstage_val.as<double>() : gam->val.as<double>();
+        a.g_stride = spill ? stage_cap : gam->nnz;
+      }
       if (gwave > 0) {
         // one launch per q3 plane: every resident wave then works on the same
         // plane, whose q-side tables stay in the XCD's L2
@@ -576,17 +692,45 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
           a.q3_lo = q3;
           a.q3_hi = q3 + 1;
           a.q3_cur = q3;
-          EPH_HIP(c, launch_rates_wave(p->precision, a, st));
+          EPH_HIP(c, launch_rates_wave(p->precision, a, st, gr ? kEmit : kRates));
         }
       } else
         EPH_HIP(c, launch_rates(p->precision, a, st));
       EPH_HIP(c, tm.mark(&eb2));
+      if (gr && spill && hrow[sb] > hrow[sa]) {  // this batch's rows to pinned host memory
+        const int64_t e0 = hrow[sa], ne = hrow[sb] - hrow[sa];
+        EPH_HIP(c, hipMemcpyAsync(gam->h_col + e0, c->gstage_col.p, sizeof(int32_t) * ne, hipMemcpyDeviceToHost, st));
+        for (int t = 0; t < nt; t++)
+          EPH_HIP(c, hipMemcpyAsync(gam->h_val + (size_t)t * gam->nnz + e0, c->gstage_val.as<double>() + (size_t)t * stage_cap,
+                                    sizeof(double) * ne, hipMemcpyDeviceToHost, st));
+        EPH_HIP(c, hipStreamSynchronize(st));
+      }
       e_batch.insert(e_batch.end(), {eb0, eb1, eb2});
       c->launches[0]++;
       c->launches[1] += gwave > 0 ? N : 1;
       g0 = g1;
     }
     EPH_HIP(c, launch_summarize(ns, c->state_cnt.as<int64_t>(), inv_tau_s, ctr + 3, st));
+    if (gr) EPH_HIP(c, launch_check_rows(ns, c->gcur.as<int64_t>(), gam->row.as<int64_t>(), ctr + 7, st));
+    if (gr) {
+      gam->h_row = std::move(hrow);
+      gr->out = gam.release();
+    }
+  } else if (gr) {  // no states: an empty set of rows
+    std::unique_ptr<eph_gamma> gam(new eph_gamma());
+    gam->ctx = c;
+    gam->nt = p->n_temps;
+    for (int t = 0; t < p->n_temps; t++) gam->temps[t] = p->temps_K[t];
+    gam->mu = p->mu_eV;
+    gam->h_row.assign(1, 0);
+    EPH_HIP(c, gam->row.ensure(sizeof(int64_t)));
+    EPH_HIP(c, launch_zero(gam->row.p, sizeof(int64_t), st));
+    if (gr->estimate_only) {
+      gr->nnz = 0;
+      gr->bytes = 8;
+    } else {
+      gr->out = gam.release();
+    }
   }
   unsigned long long hc[8];
   EPH_HIP(c, tm.mark(&e_end));
@@ -607,6 +751,11 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
   cn.n_terms = (int64_t)hc[4];
   cn.n_zero_rate = (int64_t)hc[5];
   cn.n_vertex = (int64_t)hc[6];
+  if (gr && gr->out && hc[7] != 0) {
+    delete gr->out;
+    gr->out = nullptr;
+    return fail(c, EPH_E_DEVICE, "transition rates: " + std::to_string(hc[7]) + " rows not filled to their counted length");
+  }
   if (counts) *counts = cn;
   return EPH_OK;
 }
@@ -620,6 +769,69 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
 int32_t eph_select_states(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
                           int32_t *state_n, double *energy_eV, double *vel_ms, eph_counts *counts) {
   return rates_impl(c, p, capacity, state_k, state_n, energy_eV, vel_ms, nullptr, counts, true);
+}
+
+int32_t eph_gamma_estimate(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
+                           int32_t *state_n, double *energy_eV, double *vel_ms, int64_t *nnz, int64_t *bytes) {
+  if (!c) return EPH_E_INVALID;
+  if (!nnz || !bytes) return fail(c, EPH_E_INVALID, "nnz / bytes output is NULL");
+  GammaReq gr;
+  gr.estimate_only = true;
+  eph_counts cn;
+  const int32_t r = rates_impl(c, p, capacity, state_k, state_n, energy_eV, vel_ms, nullptr, &cn, true, &gr);
+  if (r != EPH_OK) return r;
+  *nnz = gr.nnz;
+  *bytes = gr.bytes;
+  return EPH_OK;
+}
+
+int32_t eph_rates_gamma(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k, int32_t *state_n,
+                        double *energy_eV, double *vel_ms, double *inv_tau_s, eph_counts *counts, eph_gamma **out) {
+  if (!c) return EPH_E_INVALID;
+  if (!out) return fail(c, EPH_E_INVALID, "gamma output is NULL");
+  *out = nullptr;
+  GammaReq gr;
+  const int32_t r = rates_impl(c, p, capacity, state_k, state_n, energy_eV, vel_ms, inv_tau_s, counts, false, &gr);
+  if (r != EPH_OK) {
+    delete gr.out;
+    return r;
+  }
+  *out = gr.out;
+  return EPH_OK;
+}
+
+int32_t eph_gamma_info(const eph_gamma *g, int64_t *n_states, int64_t *nnz, int32_t *n_temps, int32_t *on_host,
+                       int64_t *bytes) {
+  if (!g) return EPH_E_INVALID;
+  if (n_states) *n_states = g->ns;
+  if (nnz) *nnz = g->nnz;
+  if (n_temps) *n_temps = g->nt;
+  if (on_host) *on_host = g->on_host ? 1 : 0;
+  if (bytes) *bytes = g->nnz * (4 + 8 * (int64_t)g->nt) + 8 * (g->ns + 1);
+  return EPH_OK;
+}
+
+int32_t eph_gamma_copy(const eph_gamma *g, int64_t *row_start, int32_t *col, double *val) {
+  if (!g) return EPH_E_INVALID;
+  eph_ctx *c = g->ctx;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  if (row_start) std::memcpy(row_start, g->h_row.data(), sizeof(int64_t) * (g->ns + 1));
+  if (g->nnz == 0) return EPH_OK;
+  if (g->on_host) {
+    if (col) std::memcpy(col, g->h_col, sizeof(int32_t) * g->nnz);
+    if (val) std::memcpy(val, g->h_val, sizeof(double) * g->nt * g->nnz);
+    return EPH_OK;
+  }
+  if (col) EPH_HIP(c, hipMemcpy(col, g->col.p, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToHost));
+  if (val) EPH_HIP(c, hipMemcpy(val, g->val.p, sizeof(double) * g->nt * g->nnz, hipMemcpyDeviceToHost));
+  return EPH_OK;
+}
+
+void eph_gamma_free(eph_gamma *g) {
+  if (!g) return;
+  DeviceGuard dg(g->ctx->device);
+  delete g;
 }
 
 int32_t eph_set_profiling(eph_ctx *c, int32_t on) {
@@ -677,7 +889,8 @@ namespace {
 // buffer of kSigWorkDoubles; every part of it is written before it is read.
 int32_t moments(eph_ctx *c, int64_t n_states, const double *energy_eV, const double *vel_ms,
                 const double *inv_tau_s, double mu_eV, int32_t n_temps, const double *temps_K, int64_t n_kpoints,
-                void *stream, int n_orders, double (*out)[EPH_MAX_TEMPS * 9], double *work) {
+                void *stream, int n_orders, double (*out)[EPH_MAX_TEMPS * 9], double *work,
+                const double *F = nullptr) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Units U = units();
   double *part = work;
@@ -689,7 +902,7 @@ int32_t moments(eph_ctx *c, int64_t n_states, const double *energy_eV, const dou
   const double pref = 2.0 * kCharge / ((double)n_kpoints * c->volume * 1e-30);
   for (int o = 0; o < n_orders; o++)
     EPH_HIP(c, launch_sigma(n_states, energy_eV, vel_ms, inv_tau_s, mu_eV, n_temps, kts, pref, part, kSigBlocks,
-                            outd + o * EPH_MAX_TEMPS * 9, st, o));
+                            outd + o * EPH_MAX_TEMPS * 9, st, o, F));
   EPH_HIP(c, hipMemcpyAsync(out, outd, sizeof(double) * n_orders * EPH_MAX_TEMPS * 9, hipMemcpyDeviceToHost, st));
   EPH_HIP(c, hipStreamSynchronize(st));
   return EPH_OK;
@@ -795,6 +1008,81 @@ int32_t eph_transport(eph_ctx *c, int64_t n_states, const double *energy_eV, con
       kappa_W_per_mK[t * 9 + q] = (m2[q] - k1[q]) / temps_K[t];
     }
   }
+  return EPH_OK;
+}
+
+int32_t eph_bte_iterate(eph_ctx *c, const eph_gamma *g, const double *energy_eV, const double *vel_ms,
+                        const double *inv_tau_s, int64_t n_kpoints, int32_t max_iter, double tol, void *stream,
+                        double *sigma_iter, int32_t *n_iter, double *F_out) {
+  if (!c) return EPH_E_INVALID;
+  c->err.clear();
+  if (!g || g->ctx != c) return fail(c, EPH_E_INVALID, "transition rates of another context (or NULL)");
+  if (max_iter < 0 || !(tol >= 0.0) || !sigma_iter) return fail(c, EPH_E_INVALID, "max_iter >= 0, tol >= 0, sigma_iter");
+  const int64_t ns = g->ns;
+  const int nt = g->nt;
+  int32_t r = check_moment_args(c, ns, energy_eV, vel_ms, inv_tau_s, g->mu, nt, g->temps, n_kpoints);
+  if (r != EPH_OK) return r;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return fail(c, EPH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  EPH_HIP(c, c->sig_part.ensure(sizeof(double) * kSigWorkDoubles));
+  const size_t fsz = (size_t)nt * ns * 3;
+  EPH_HIP(c, c->bte_f.ensure(sizeof(double) * 3 * std::max<size_t>(fsz, 1)));
+  double *F0 = c->bte_f.as<double>(), *Fa = F0 + fsz, *Fb = Fa + fsz;
+  EPH_HIP(c, launch_f0(ns, nt, vel_ms, inv_tau_s, F0, st));
+  if (g->on_host && g->nnz > 0) {
+    EPH_HIP(c, c->gstage_col.ensure(sizeof(int32_t) * g->stage_nnz));
+    EPH_HIP(c, c->gstage_val.ensure(sizeof(double) * g->stage_nnz));
+  }
+  double m[1][EPH_MAX_TEMPS * 9];
+  r = moments(c, ns, energy_eV, vel_ms, inv_tau_s, g->mu, nt, g->temps, n_kpoints, stream, 1, m, c->sig_part.as<double>(), F0);
+  if (r != EPH_OK) return r;
+  for (int q = 0; q < nt * 9; q++) sigma_iter[q] = m[0][q];
+  const double *Fin = F0;
+  double *Fout = Fa;
+  int32_t done = 0;
+  for (int32_t it = 1; it <= max_iter; it++) {
+    for (int t = 0; t < nt; t++) {
+      const double *itau = inv_tau_s + (size_t)t * ns;
+      const size_t fo = (size_t)t * ns * 3;
+      if (!g->on_host) {
+        EPH_HIP(c, launch_bte_step(0, ns, g->row.as<int64_t>(), 0, g->col.as<int32_t>(),
+                                   g->val.as<double>() + (size_t)t * g->nnz, itau, F0 + fo, Fin + fo, Fout + fo, st));
+        continue;
+      }
+      // rows in batches whose entries fit the staging buffer
+      int64_t r0 = 0;
+      while (r0 < ns) {
+        int64_t r1 = r0 + 1;
+        while (r1 < ns && g->h_row[r1 + 1] - g->h_row[r0] <= g->stage_nnz) r1++;
+        const int64_t e0 = g->h_row[r0], ne = g->h_row[r1] - e0;
+        if (ne > 0) {
+          EPH_HIP(c, hipMemcpyAsync(c->gstage_col.p, g->h_col + e0, sizeof(int32_t) * ne, hipMemcpyHostToDevice, st));
+          EPH_HIP(c, hipMemcpyAsync(c->gstage_val.p, g->h_val + (size_t)t * g->nnz + e0, sizeof(double) * ne,
+                                    hipMemcpyHostToDevice, st));
+        }
+        EPH_HIP(c, launch_bte_step(r0, r1, g->row.as<int64_t>(), e0, c->gstage_col.as<int32_t>(),
+                                   c->gstage_val.as<double>(), itau, F0 + fo, Fin + fo, Fout + fo, st));
+        r0 = r1;
+      }
+    }
+    r = moments(c, ns, energy_eV, vel_ms, inv_tau_s, g->mu, nt, g->temps, n_kpoints, stream, 1, m,
+                c->sig_part.as<double>(), Fout);
+    if (r != EPH_OK) return r;
+    double dmax = 0.0, smax = 0.0;
+    for (int q = 0; q < nt * 9; q++) {
+      sigma_iter[(size_t)it * nt * 9 + q] = m[0][q];
+      dmax = std::max(dmax, std::fabs(m[0][q] - sigma_iter[(size_t)(it - 1) * nt * 9 + q]));
+      smax = std::max(smax, std::fabs(m[0][q]));
+    }
+    done = it;
+    Fin = Fout;
+    Fout = (Fout == Fa) ? Fb : Fa;
+    if (dmax <= tol * smax) break;
+  }
+  if (F_out && fsz > 0) EPH_HIP(c, hipMemcpyAsync(F_out, Fin, sizeof(double) * fsz, hipMemcpyDeviceToDevice, st));
+  EPH_HIP(c, hipStreamSynchronize(st));
+  if (n_iter) *n_iter = done;
   return EPH_OK;
 }
 

@@ -92,6 +92,10 @@ struct eph_ctx {
   eph::DevBuf sig_part;                 // sigma partial sums
   double *scratch = nullptr;            // device address of the static workspace (eph_conductivity_noalloc)
   eph::DevBuf state_cnt;                // per-state int64 counts
+  eph::DevBuf stidx;                    // [N^3][nw] state index table (transition rates)
+  eph::DevBuf gcur;                     // per-state transition-rate counts / cursors
+  eph::DevBuf gstage_col, gstage_val;   // staging of spilled transition rates
+  eph::DevBuf bte_f;                    // F0, F, F' of the iteration
   eph::DevBuf occ;                      // Fermi and Bose factor tables
   // stage timing
   bool profiling = false;
@@ -102,6 +106,27 @@ struct eph_ctx {
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);
   }
+};
+
+// Transition rates of the iterative BTE, row by row (CSR): row s holds the
+// entries of state s, each a final-state index (into the same state list)
+// and one value per temperature.  Kept in device memory, or in pinned host
+// memory when it does not fit the device budget (streamed back in batches
+// of rows for every iteration).
+struct eph_gamma {
+  eph_ctx *ctx = nullptr;
+  int64_t ns = 0, nnz = 0;
+  int nt = 0;
+  double temps[EPH_MAX_TEMPS] = {0, 0, 0, 0};
+  double mu = 0;
+  bool on_host = false;
+  std::vector<int64_t> h_row;   // [ns+1] row starts (host copy)
+  eph::DevBuf row;              // [ns+1] row starts (device)
+  eph::DevBuf col, val;         // device entries: col [nnz] int32, val [nt][nnz] (resident)
+  int32_t *h_col = nullptr;     // pinned host entries (spilled)
+  double *h_val = nullptr;      // [nt][nnz]
+  int64_t stage_nnz = 0;        // entries per staging batch (spilled)
+  ~eph_gamma();
 };
 
 namespace eph {
@@ -182,12 +207,21 @@ struct RatesArgs {
   const double *occ_n;             // [N^3][nm][EPH_MAX_TEMPS] Bose factors, 0 below omega_cut
   int q3_lo, q3_hi;                // q3 planes of this launch (wave kernel)
   int q3_cur;                      // the plane (wave kernel launches one plane at a time)
+  // transition rates of the iterative BTE (wave kernel, FP64, count and emit modes)
+  const int32_t *stidx;            // [N^3][nw] index of state (k, m) in the list, -1 if none
+  int64_t *g_cursor;               // [ns_total] per-state count (count mode) or next position (emit)
+  int32_t *g_col;                  // emitted final-state indices, position - g_base
+  double *g_val;                   // emitted values [t][g_stride], 1/s
+  int64_t g_stride;                // temperature stride of g_val
+  int64_t g_base;                  // position of g_col[0] / g_val[0]
 };
+// rate-kernel modes (wave kernel)
+constexpr int kRates = 0, kCount = 1, kEmit = 2;
 hipError_t launch_rates(int precision, const RatesArgs &a, hipStream_t st);
 // Wave-autonomous rate kernel; rates_wave_group gives its states per group
 // (0 when the shape is not served and launch_rates must be used).
 int rates_wave_group(int nw, int nm, RpBox box, int N, int precision);
-hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st);
+hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st, int mode = kRates);
 // Occupation tables: occ_f[k][n][t] = 1/(exp((eps-mu)/kT_t)+1),
 // occ_n[q][nu][t] = 1/expm1(hbar w/kT_t) (0 when hbar w < wcut).
 hipError_t launch_occupations(int64_t nq, int nw, int nm, const double *eps, const double *om, double mu,
@@ -197,9 +231,19 @@ hipError_t launch_occupations(int64_t nq, int nw, int nm, const double *eps, con
 // sigma partial sums per block, then out[T*9 + ab] = pref * sum of partials
 // (partials: [nblk][EPH_MAX_TEMPS*9], out: [EPH_MAX_TEMPS*9], kts: device [nt]).
 // order n weights each state by (eps - mu)^n (n = 0: sigma)
+// F (optional, [nt][ns][3]) replaces v_b tau by the mean free path F_b.
 hipError_t launch_sigma(int64_t ns, const double *e, const double *v, const double *inv_tau, double mu,
                         int nt, const double *kts, double pref, double *partials, int nblk, double *out,
-                        hipStream_t st, int order = 0);
+                        hipStream_t st, int order = 0, const double *F = nullptr);
+// iterative BTE (k_bte.hip)
+hipError_t launch_state_index(int64_t nq, int nw, int64_t ns, const int32_t *sk, const int32_t *sn, int32_t *stidx,
+                              hipStream_t st);
+hipError_t launch_f0(int64_t ns, int nt, const double *vel, const double *inv_tau, double *F0, hipStream_t st);
+hipError_t launch_bte_step(int64_t r0, int64_t r1, const int64_t *row_start, int64_t base, const int32_t *col,
+                           const double *val, const double *inv_tau, const double *F0, const double *Fin, double *Fout,
+                           hipStream_t st);
+hipError_t launch_check_rows(int64_t ns, const int64_t *cursor, const int64_t *row_start, unsigned long long *bad,
+                             hipStream_t st);
 // out[t] = pref * sum_{k, blo <= n <= bhi} f(eps_nk) (partials: [nblk][EPH_MAX_TEMPS])
 hipError_t launch_density(int64_t nk, int nw, const double *eps, int blo, int bhi, double mu, int nt,
                           const double *kts, double pref, double *partials, int nblk, double *out, hipStream_t st);

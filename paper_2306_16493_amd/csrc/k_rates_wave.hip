@@ -4,12 +4,16 @@
 
 namespace eph {
 namespace wave {
-template <class T, int NM>
+template <class T, int NM, int MODE>
 hipError_t dispatch_nm(const RatesArgs &a, hipStream_t st);
-extern template hipError_t dispatch_nm<double, 3>(const RatesArgs &, hipStream_t);
-extern template hipError_t dispatch_nm<double, 6>(const RatesArgs &, hipStream_t);
-extern template hipError_t dispatch_nm<float, 3>(const RatesArgs &, hipStream_t);
-extern template hipError_t dispatch_nm<float, 6>(const RatesArgs &, hipStream_t);
+extern template hipError_t dispatch_nm<double, 3, kRates>(const RatesArgs &, hipStream_t);
+extern template hipError_t dispatch_nm<double, 6, kRates>(const RatesArgs &, hipStream_t);
+extern template hipError_t dispatch_nm<float, 3, kRates>(const RatesArgs &, hipStream_t);
+extern template hipError_t dispatch_nm<float, 6, kRates>(const RatesArgs &, hipStream_t);
+extern template hipError_t dispatch_nm<double, 3, kCount>(const RatesArgs &, hipStream_t);
+extern template hipError_t dispatch_nm<double, 6, kCount>(const RatesArgs &, hipStream_t);
+extern template hipError_t dispatch_nm<double, 3, kEmit>(const RatesArgs &, hipStream_t);
+extern template hipError_t dispatch_nm<double, 6, kEmit>(const RatesArgs &, hipStream_t);
 }  // namespace wave
 
 // Shapes served by the wave-autonomous kernel: a cubic Rp box of edge 4 or
@@ -26,10 +30,20 @@ int rates_wave_group(int nw, int nm, RpBox box, int N, int precision) {
   return 0;
 }
 
-hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st) {
+// mode kCount / kEmit (transition rates) are FP64 only.
+hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st, int mode) {
   if (a.ng <= 0) return hipSuccess;
-  if (precision == EPH_FP64) return a.nm == 3 ? wave::dispatch_nm<double, 3>(a, st) : wave::dispatch_nm<double, 6>(a, st);
-  return a.nm == 3 ? wave::dispatch_nm<float, 3>(a, st) : wave::dispatch_nm<float, 6>(a, st);
+  const bool m3 = a.nm == 3;
+  if (mode == kCount) {
+    if (precision != EPH_FP64) return hipErrorNotSupported;
+    return m3 ? wave::dispatch_nm<double, 3, kCount>(a, st) : wave::dispatch_nm<double, 6, kCount>(a, st);
+  }
+  if (mode == kEmit) {
+    if (precision != EPH_FP64) return hipErrorNotSupported;
+    return m3 ? wave::dispatch_nm<double, 3, kEmit>(a, st) : wave::dispatch_nm<double, 6, kEmit>(a, st);
+  }
+  if (precision == EPH_FP64) return m3 ? wave::dispatch_nm<double, 3, kRates>(a, st) : wave::dispatch_nm<double, 6, kRates>(a, st);
+  return m3 ? wave::dispatch_nm<float, 3, kRates>(a, st) : wave::dispatch_nm<float, 6, kRates>(a, st);
 }
 
 }  // namespace eph

@@ -3,6 +3,6 @@
 
 namespace eph {
 namespace wave {
-template hipError_t dispatch_nm<double, 6>(const RatesArgs &, hipStream_t);
+template hipError_t dispatch_nm<double, 6, kRates>(const RatesArgs &, hipStream_t);
 }  // namespace wave
 }  // namespace eph

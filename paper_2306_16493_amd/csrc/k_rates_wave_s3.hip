@@ -3,6 +3,6 @@
 
 namespace eph {
 namespace wave {
-template hipError_t dispatch_nm<float, 3>(const RatesArgs &, hipStream_t);
+template hipError_t dispatch_nm<float, 3, kRates>(const RatesArgs &, hipStream_t);
 }  // namespace wave
 }  // namespace eph

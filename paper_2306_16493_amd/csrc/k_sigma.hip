@@ -2,7 +2,8 @@
 // density, and small element-wise helpers (gfx950).
 //
 // M_n,ab(T) = 2 e^2/(N_k V) sum_s v_a v_b tau_s f(1-f)/(k_B T) (eps_s - mu)^n
-// (n = 0 is sigma; eps in eV): each block reduces a contiguous chunk of
+// (n = 0 is sigma; eps in eV), or with v_b tau_s replaced by the mean free
+// path F_b of the iterative solution: each block reduces a contiguous chunk of
 // states with Neumaier-compensated per-thread sums and a fixed butterfly,
 // writing [block][T][9] partials; a one-block kernel then adds the partials
 // in block order and applies the prefactor.  The carrier density sums f over
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(kSigThreads) void sigma_kernel(int64_t ns, const do
                                                              const double *__restrict__ inv_tau, double mu, int nt,
                                                              const double *__restrict__ kts,
                                                              double *__restrict__ partials, int64_t chunk,
-                                                             int order) {
+                                                             int order, const double *__restrict__ F) {
   __shared__ double red[kSigThreads / 64][EPH_MAX_TEMPS * 9];
   const int64_t b0 = blockIdx.x * chunk, b1 = min(ns, b0 + chunk);
   double s[EPH_MAX_TEMPS][9], c[EPH_MAX_TEMPS][9];
@@ -43,6 +44,14 @@ __global__ __launch_bounds__(kSigThreads) void sigma_kernel(int64_t ns, const do
       const double kt = kts[t];
       const double f = 1.0 / (exp((e[i] - mu) / kt) + 1.0);
       const double de = e[i] - mu;
+      if (F) {  // mean free paths of the iterative solution: v_a F_b in place of v_a v_b tau
+        const double *fb = F + ((int64_t)t * ns + i) * 3;
+        const double w = f * (1.0 - f) / kt * (order == 0 ? 1.0 : order == 1 ? de : de * de);
+        const double vf[9] = {vx * fb[0], vx * fb[1], vx * fb[2], vy * fb[0], vy * fb[1],
+                              vy * fb[2], vz * fb[0], vz * fb[1], vz * fb[2]};
+        for (int q = 0; q < 9; q++) neumaier(s[t][q], c[t][q], vf[q] * w);
+        continue;
+      }
       const double w = f * (1.0 - f) / kt / it * (order == 0 ? 1.0 : order == 1 ? de : de * de);
       for (int q = 0; q < 9; q++) neumaier(s[t][q], c[t][q], vv[q] * w);
     }
@@ -125,11 +134,11 @@ __global__ void to_f32_kernel(int64_t n, const double2 *__restrict__ in, float2 
 
 hipError_t launch_sigma(int64_t ns, const double *e, const double *v, const double *inv_tau, double mu, int nt,
                         const double *kts, double pref, double *partials, int nblk, double *out,
-                        hipStream_t st, int order) {
+                        hipStream_t st, int order, const double *F) {
   int64_t chunk = (ns + nblk - 1) / nblk;
   if (chunk < 1) chunk = 1;
   hipLaunchKernelGGL(sigma_kernel, dim3(nblk), dim3(kSigThreads), 0, st, ns, e, v, inv_tau, mu, nt, kts, partials,
-                     chunk, order);
+                     chunk, order, F);
   hipLaunchKernelGGL(sigma_final_kernel, dim3(1), dim3(64), 0, st, nblk, partials, pref, out);
   return hipGetLastError();
 }

@@ -59,7 +59,11 @@ struct WaveLayout {
 #ifndef EPH_WAVE_OCC
 #define EPH_WAVE_OCC 2
 #endif
-template <class T, int NW, int NM, int GW, int NB, int LPL>
+// MODE: kRates computes 1/tau; kCount only counts, per state, the transition
+// rates to final states in the state list (no transforms, no vertices);
+// kEmit computes 1/tau and also writes those transition rates (the summed
+// terms of each (state, q, m) vertex) at the state's running cursor.
+template <class T, int NW, int NM, int GW, int NB, int LPL, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OCC))) void rates_wave_kernel(
     RatesArgs a) {
   using C2 = typename V2<T>::t;
@@ -156,6 +160,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
     for (int t = 0; t < EPH_MAX_TEMPS; t++) acc[s][t] = 0.0;
   }
   unsigned long long my_nkq = 0, my_nv = 0;
+  // transition rates: per-state counts (kCount, per lane) or running write
+  // positions (kEmit, wave-uniform)
+  int64_t gcur[GW];
+#pragma unroll
+  for (int ss = 0; ss < GW; ss++) gcur[ss] = (MODE == kEmit && ss < S) ? a.g_cursor[s0 + ss] : 0;
 
   // pair slots of this lane: P = lane + 64 j -> (s, p1, c) = (P / (NB C), (P / C) % NB, P % C)
   T yr[NPAIR][NB], yi[NPAIR][NB];
@@ -195,7 +204,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   auto vdrain = [&](int count) __attribute__((always_inline)) {
     for (int base = 0; base < count; base += 64) {
       const int i = base + lane;
-      if (i >= count) continue;
+      if constexpr (MODE == kCount) {
+        // only which final states the kept vertices reach
+        if (i < count) {
+          const uint2 it = sV[i];
+          const int p1 = (int)(it.x & 1023u), s = (int)(it.y & 7u), m = (int)((it.y >> 3) & 7u);
+          const int q2 = (int)((it.y >> 18) & 1023u);
+          const int p2l = (k2 + q2 >= N) ? k2 + q2 - N : k2 + q2;
+          const int p3l = (k3 + a.q3_cur >= N) ? k3 + a.q3_cur - N : k3 + a.q3_cur;
+          const int64_t pidx = p1 + (int64_t)N * (p2l + (int64_t)N * p3l);
+          const bool in_list = a.stidx[pidx * NW + m] >= 0;
+#pragma unroll
+          for (int ss = 0; ss < GW; ss++) gcur[ss] += (in_list && ss == s) ? 1 : 0;
+        }
+        continue;
+      }
+      int e_state = -1, e_col = -1;  // transition rate of this lane's vertex (kEmit)
+      double e_val[EPH_MAX_TEMPS];
+      if (i < count) {
       // everything the vertex needs is in its queue item (no table lookups)
       const uint2 it = sV[i];
       const int p1 = (int)(it.x & 1023u), q1 = (int)((it.x >> 10) & 1023u), i1 = (int)((it.x >> 20) & 1023u);
@@ -328,6 +354,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 #pragma unroll
         for (int t = 0; t < EPH_MAX_TEMPS; t++) acc[ss][t] += me ? contrib[t] : 0.0;
       }
+      if constexpr (MODE == kEmit) {
+        e_col = a.stidx[pidx * NW + m];
+        e_state = s;
+#pragma unroll
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) e_val[t] = a.pref * contrib[t];
+      }
+      }
+      if constexpr (MODE == kEmit) {
+        // entries of one state go to consecutive positions in lane order
+        // (all lanes take part in the ballots)
+        const bool keep = e_col >= 0;
+#pragma unroll
+        for (int ss = 0; ss < GW; ss++) {
+          const unsigned long long bits = __ballot(keep && e_state == ss);
+          if (keep && e_state == ss) {
+            const int64_t e = gcur[ss] + __popcll(bits & ((1ull << lane) - 1ull)) - a.g_base;
+            a.g_col[e] = e_col;
+            for (int t = 0; t < EPH_MAX_TEMPS; t++)
+              if (t < nt) a.g_val[(int64_t)t * a.g_stride + e] = e_val[t];
+          }
+          gcur[ss] += __popcll(bits);
+        }
+      }
     }
   };
   auto vpop = [&](int n) __attribute__((always_inline)) {
@@ -430,7 +479,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
     for (int j = 0; j < NPAIR; j++)
 #pragma unroll
       for (int p2 = 0; p2 < NB; p2++) yr[j][p2] = yi[j][p2] = 0;
-    {
+    if constexpr (MODE != kCount) {
       int i3 = imod(q3 * lo3, N);
 #pragma unroll 1
       for (int p3 = 0; p3 < NB; p3++) {
@@ -502,7 +551,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 #pragma unroll
       for (int j = 0; j < NPAIR; j++) {
         const int P = lane + 64 * j;
-        if (P < GW * NB * C) {
+        if (MODE != kCount && P < GW * NB * C) {
           T r = 0, i = 0;
 #pragma unroll
           for (int p2 = 0; p2 < NB; p2++) cmac<T>(r, i, ph2[p2].x, ph2[p2].y, yr[j][p2], yi[j][p2]);
@@ -566,6 +615,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   __syncwarp();
   vdrain(vn);
 
+  if constexpr (MODE == kCount) {
+    // per-state counts of transition rates, added up over the plane launches
+#pragma unroll
+    for (int s = 0; s < GW; s++) {
+      int64_t c = gcur[s];
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, 64);
+      if (lane == 0 && s < S) a.g_cursor[s0 + s] += c;
+    }
+    return;
+  }
+  if constexpr (MODE == kEmit) {
+#pragma unroll
+    for (int s = 0; s < GW; s++)
+      if (lane == 0 && s < S) a.g_cursor[s0 + s] = gcur[s];
+  }
+
   // ---- fixed-order reductions; q3 slabs add up in launch order ----
 #pragma unroll
   for (int s = 0; s < GW; s++) {
@@ -603,12 +669,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   }
 }
 
-template <class T, int NW, int NM, int GW, int NB, int LPL>
+template <class T, int NW, int NM, int GW, int NB, int LPL, int MODE>
 hipError_t launch_wave_l(const RatesArgs &a, hipStream_t st) {
   using LY = WaveLayout<T, NW, NM, GW, NB, typename std::conditional<(LPL >= 16), float, double>::type>;
   const size_t sh = LY::total(a.N);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL>;
+  auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL, MODE>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
   const int64_t nblk = (a.ng + 3) / 4;
@@ -617,26 +683,27 @@ hipError_t launch_wave_l(const RatesArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class T, int NW, int NM, int GW, int NB>
+template <class T, int NW, int NM, int GW, int NB, int MODE>
 hipError_t launch_wave(const RatesArgs &a, hipStream_t st) {
   const int ln = a.N * NW;
-  if (ln <= 512) return launch_wave_l<T, NW, NM, GW, NB, 8>(a, st);
-  if (ln <= 1024) return launch_wave_l<T, NW, NM, GW, NB, 16>(a, st);
-  if (ln <= 2048) return launch_wave_l<T, NW, NM, GW, NB, 32>(a, st);
+  if (ln <= 512) return launch_wave_l<T, NW, NM, GW, NB, 8, MODE>(a, st);
+  if (ln <= 1024) return launch_wave_l<T, NW, NM, GW, NB, 16, MODE>(a, st);
+  if (ln <= 2048) return launch_wave_l<T, NW, NM, GW, NB, 32, MODE>(a, st);
   return hipErrorNotSupported;
 }
 
 
-// Launch for one (precision, modes) pair: dispatch on the orbital count and
-// the Rp box edge.  GW (states per group) must match rates_wave_group.
-template <class T, int NM>
+// Launch for one (precision, modes, mode) triple: dispatch on the orbital
+// count and the Rp box edge.  GW (states per group) must match
+// rates_wave_group.
+template <class T, int NM, int MODE>
 hipError_t dispatch_nm(const RatesArgs &a, hipStream_t st) {
   const int nb = a.box.n[0];
-#define EPH_W(NW_, GW_)                                         \
-  if (a.nw == NW_) {                                            \
-    if (nb == 4) return launch_wave<T, NW_, NM, GW_, 4>(a, st); \
-    if (nb == 6) return launch_wave<T, NW_, NM, GW_, 6>(a, st); \
-    return hipErrorNotSupported;                                \
+#define EPH_W(NW_, GW_)                                               \
+  if (a.nw == NW_) {                                                  \
+    if (nb == 4) return launch_wave<T, NW_, NM, GW_, 4, MODE>(a, st); \
+    if (nb == 6) return launch_wave<T, NW_, NM, GW_, 6, MODE>(a, st); \
+    return hipErrorNotSupported;                                      \
   }
   if constexpr (NM == 3) {
     EPH_W(1, 2)

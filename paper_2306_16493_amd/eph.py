@@ -27,7 +27,8 @@ EXPORTS = ("eph_load_wannier", "eph_free", "eph_last_error", "eph_scattering_rat
            "eph_conductivity", "eph_conductivity_noalloc", "eph_transport", "eph_carrier_density", "eph_mobility",
            "eph_set_profiling", "eph_stage_times", "eph_mlp_create", "eph_mlp_free", "eph_mlp_params",
            "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient", "eph_mlp_predict", "eph_mlp_blend",
-           "eph_merge_rates")
+           "eph_merge_rates", "eph_gamma_estimate", "eph_rates_gamma", "eph_gamma_info", "eph_gamma_copy",
+           "eph_gamma_free", "eph_bte_iterate")
 
 
 class EphError(RuntimeError):
@@ -107,6 +108,18 @@ def lib():
         L.eph_transport.argtypes = [vp, i64, vp, vp, vp, f64, i32, vp, i64, vp, vp, vp, vp]
         L.eph_carrier_density.argtypes = [vp, i32, i32, i32, f64, i32, vp, vp, vp]
         L.eph_mobility.argtypes = [i32, vp, vp, vp]
+        L.eph_gamma_estimate.argtypes = [vp, C.POINTER(RatesParams), i64, vp, vp, vp, vp, C.POINTER(i64),
+                                         C.POINTER(i64)]
+        L.eph_rates_gamma.argtypes = [vp, C.POINTER(RatesParams), i64, vp, vp, vp, vp, vp, C.POINTER(Counts),
+                                      C.POINTER(vp)]
+        L.eph_gamma_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
+                                     C.POINTER(i64)]
+        L.eph_gamma_copy.argtypes = [vp, vp, vp, vp]
+        L.eph_gamma_free.argtypes = [vp]
+        L.eph_gamma_free.restype = None
+        L.eph_bte_iterate.argtypes = [vp, vp, vp, vp, vp, i64, i32, f64, vp, vp, C.POINTER(i32), vp]
+        for f in ("eph_gamma_estimate", "eph_rates_gamma", "eph_gamma_info", "eph_gamma_copy", "eph_bte_iterate"):
+            getattr(L, f).restype = C.c_int32
         for f in ("eph_mlp_create", "eph_mlp_params", "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient",
                   "eph_mlp_predict", "eph_mlp_blend", "eph_merge_rates", "eph_transport", "eph_carrier_density",
                   "eph_mobility"):
@@ -321,8 +334,94 @@ def mobility(sigma, n_per_m3):
     return out
 
 
+class Gamma:
+    """Transition rates of the iterative BTE (an eph_gamma handle)."""
+
+    def __init__(self, ctx, handle):
+        self.ctx, self._h = ctx, handle
+
+    def info(self):
+        ns, nnz, nt, host, b = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64()
+        self.ctx._check(lib().eph_gamma_info(self._h, C.byref(ns), C.byref(nnz), C.byref(nt), C.byref(host),
+                                             C.byref(b)))
+        return dict(n_states=ns.value, nnz=nnz.value, n_temps=nt.value, on_host=bool(host.value), bytes=b.value)
+
+    def rows(self):
+        """(row_start [ns+1], col [nnz], val [nt][nnz]) as numpy arrays."""
+        i = self.info()
+        rs = np.zeros(i["n_states"] + 1, np.int64)
+        col = np.zeros(max(i["nnz"], 1), np.int32)
+        val = np.zeros((i["n_temps"], max(i["nnz"], 1)))
+        self.ctx._check(lib().eph_gamma_copy(self._h, _ptr(rs), _ptr(col), _ptr(val)))
+        return rs, col[:i["nnz"]], val[:, :i["nnz"]]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().eph_gamma_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+class _Bte:
+    """Iterative BTE entry points of a Context (mixed into Context below)."""
+
+    def gamma_estimate(self, params):
+        """(n_states, nnz, bytes) of the transition rates, from the sieve only."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        ns = self.count_states(params)
+        cap = max(ns, 1)
+        k = torch.empty(cap, dtype=torch.int32, device=dev)
+        n = torch.empty(cap, dtype=torch.int32, device=dev)
+        e = torch.empty(cap, dtype=torch.float64, device=dev)
+        v = torch.empty(cap, 3, dtype=torch.float64, device=dev)
+        nnz, b = C.c_int64(), C.c_int64()
+        self._check(lib().eph_gamma_estimate(self._h, C.byref(params), ns, _dptr(k), _dptr(n), _dptr(e), _dptr(v),
+                                             C.byref(nnz), C.byref(b)))
+        return ns, nnz.value, b.value
+
+    def rates_gamma(self, params):
+        """eph_scattering_rates plus the transition rates: (RatesResult, Gamma)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        ns = self.count_states(params)
+        nt = int(params.n_temps)
+        cap = max(ns, 1)
+        bufs = dict(k=torch.empty(cap, dtype=torch.int32, device=dev),
+                    n=torch.empty(cap, dtype=torch.int32, device=dev),
+                    e=torch.empty(cap, dtype=torch.float64, device=dev),
+                    v=torch.empty(cap, 3, dtype=torch.float64, device=dev),
+                    it=torch.empty(nt * cap, dtype=torch.float64, device=dev))
+        cnt = Counts()
+        h = C.c_void_p()
+        self._check(lib().eph_rates_gamma(self._h, C.byref(params), ns, _dptr(bufs["k"]), _dptr(bufs["n"]),
+                                          _dptr(bufs["e"]), _dptr(bufs["v"]), _dptr(bufs["it"]), C.byref(cnt),
+                                          C.byref(h)))
+        res = RatesResult(bufs["k"][:ns], bufs["n"][:ns], bufs["e"][:ns], bufs["v"][:ns],
+                          bufs["it"][:nt * ns].view(nt, ns), cnt.as_dict())
+        return res, Gamma(self, h)
+
+    def bte_iterate(self, gamma, res, n_kpoints, max_iter=20, tol=1e-6, want_f=False, stream=None):
+        """(sigma per iteration [n_done+1][nt][3][3], n_done, F or None)."""
+        import torch
+        nt = int(res.inv_tau.shape[0])
+        ns = int(res.energy.shape[0])
+        sig = np.zeros((max_iter + 1, nt, 3, 3))
+        nd = C.c_int32()
+        F = torch.empty((nt, max(ns, 1), 3), dtype=torch.float64, device=res.energy.device) if want_f else None
+        self._check(lib().eph_bte_iterate(self._h, gamma._h, _dptr(res.energy.contiguous()),
+                                          _dptr(res.vel.contiguous()), _dptr(res.inv_tau.contiguous()),
+                                          int(n_kpoints), int(max_iter), float(tol),
+                                          C.c_void_p(stream) if stream else None, _ptr(sig), C.byref(nd),
+                                          _dptr(F) if F is not None else None))
+        return sig[:nd.value + 1], nd.value, (F[:, :ns] if F is not None else None)
+
+
 for _name in ("transport", "carrier_density"):
     setattr(Context, _name, getattr(_Transport, _name))
+for _name in ("gamma_estimate", "rates_gamma", "bte_iterate"):
+    setattr(Context, _name, getattr(_Bte, _name))
 
 
 class Mlp:
