@@ -4,13 +4,20 @@ One step = one eph_scattering_rates call (grid tables, states, Re transform,
 fused rate kernel) + one eph_conductivity call, on the Al-like 100^3 k x
 100^3 q workload with the 100/300/500 K batch (synthetic inputs, seeded).
 
+The three forms (FP64, FP32, BF16x3 transforms) are each timed for a few
+steps; the headline is the fastest form whose sigma is within 1e-3 relative
+of the FP64 sigma of the same run, timed for --steps after --warmup.
+
 Prints ONE JSON line:
   value       (k,q) pairs with >= 1 kept term, per second of step time
   ms_per_step step time = the sigma wall time (rates + conductivity)
-  roofline    the fused rate kernel against the FP64 vector peak, with the
-              flops of the algorithm it runs (from the call's own counts)
-              over its HIP-event-timed duration
-  cpu_baseline the FP64 C oracle on a seeded sample of k points (all q)
+  roofline    the fused rate kernel of the headline form against its vector
+              peak (FP64 78.6, FP32 157.3 TFLOP/s), with the flops of the
+              algorithm it runs (from the call's own counts) over its
+              HIP-event-timed duration; roofline_fp64 the same for FP64
+  forms       every form's step time, speedup over FP64 and sigma error
+  cpu_baseline the FP64 C oracle on a seeded sample of k points (all q),
+              on all host threads and on one
 """
 import argparse
 import json
@@ -22,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "(k,q) el-ph pair evals/s + σ wall time at ≤1e-3 rel σ error vs FP64"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 157.3}   # FP64 / FP32 vector peaks of MI355X
+# FP64 / FP32 vector peaks of MI355X; the rate kernel of the BF16x3 form runs in FP32
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 157.3}
 
 
 def measured_traffic(workload, precision):
@@ -56,7 +64,21 @@ def rate_kernel_flops(counts, ns, N, box, C, nm, nw):
     return y + z + v
 
 
-def cpu_baseline(system, w, mu, lo, hi, state_k, n_pick):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(system, w, mu, lo, hi, state_k, n_pick, n_pick_single=2):
+    """The FP64 oracle's rate loop on a seeded sample of k points (all q),
+    on all the threads its OpenMP runtime uses and on one thread."""
+    import ctypes
     import numpy as np
     import oracle
     from oracle import Oracle
@@ -70,13 +92,31 @@ def cpu_baseline(system, w, mu, lo, hi, state_k, n_pick):
     kall = np.unique(state_k)
     kpick = np.sort(rng.choice(kall, size=min(n_pick, kall.size), replace=False))
     sk, sn = o.select_states(eps, w.band_lo, w.band_hi, lo, hi, k_subset=kpick)
+    threads = int(oracle.lib().orc_num_threads())
     t0 = time.perf_counter()
     r = o.rates(N, eps, evec, om, u, sk, sn, mu, w.temps, w.eta)
     t = time.perf_counter() - t0
-    return {"value": r["n_kq"] / t, "unit": "(k,q) pairs/s", "cores": int(oracle.lib().orc_num_threads()),
-            "kind": "oracle",
-            "sample": f"{kpick.size} seeded k points ({sk.size} states, {r['n_kq']} (k,q) pairs, all {N}^3 q) of "
-                      f"{w.name}; rate loop {t:.2f} s; full-grid oracle tables {t_tables:.2f} s not counted"}
+    out = {"value": r["n_kq"] / t, "unit": "(k,q) pairs/s", "cores": threads, "kind": "oracle",
+           "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"{kpick.size} seeded k points ({sk.size} states, {r['n_kq']} (k,q) pairs, all {N}^3 q) of "
+                     f"{w.name}; rate loop {t:.2f} s on {threads} threads; full-grid oracle tables "
+                     f"{t_tables:.2f} s not counted"}
+    # one thread, on the first k points of the same sample
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        k1 = kpick[:n_pick_single]
+        sk1, sn1 = o.select_states(eps, w.band_lo, w.band_hi, lo, hi, k_subset=k1)
+        t0 = time.perf_counter()
+        r1 = o.rates(N, eps, evec, om, u, sk1, sn1, mu, w.temps, w.eta)
+        t1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        out["single_thread"] = {"value": r1["n_kq"] / t1, "unit": "(k,q) pairs/s", "cores": 1,
+                                "sample": f"{k1.size} of the same k points ({sk1.size} states, {r1['n_kq']} "
+                                          f"(k,q) pairs); rate loop {t1:.2f} s"}
+    except OSError:
+        out["single_thread"] = None
+    return out
 
 
 def main():
@@ -88,13 +128,13 @@ def main():
                     help="default al_fcc_100 (bench line), si_fcc_150 (--report precision), al_fcc_200 (--report "
                          "surrogate)")
     ap.add_argument("--grid", type=int, default=None)
-    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--precision", default="auto",
+                    help="form of the headline: auto (the fastest within 1e-3 relative sigma error of the FP64 "
+                         "run), fp64, fp32 or bf16x3")
     ap.add_argument("--cpu-sample", type=int, default=40, help="k points of the oracle sample (0 = skip)")
-    ap.add_argument("--report", choices=["precision", "surrogate"], default=None,
+    ap.add_argument("--report", choices=["precision", "surrogate", "ablation"], default=None,
                     help="instead of the bench line, measure the FP32/BF16x3 forms or the surrogate on "
                          "their own workloads (one JSON line)")
-    ap.add_argument("--fp32-form", type=int, default=1,
-                    help="with --precision fp64, also time the FP32 form (extra 'fp32_form' key; 0 = skip)")
     ap.add_argument("--subset-frac", type=float, default=0.01, help="k-point fraction of --report precision")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
@@ -118,6 +158,10 @@ def main():
         wl = args.workload or "si_fcc_150"
         print(json.dumps(reports.precision(wl, args.subset_frac, grid=args.grid)), flush=True)
         return
+    if args.report == "ablation":
+        from paper_2306_16493_amd import reports
+        print(json.dumps(reports.ablation(args.workload or "al_fcc_100", grid=args.grid or 40)), flush=True)
+        return
     if args.report == "surrogate":
         from paper_2306_16493_amd import reports
         wl = args.workload or "al_fcc_200"
@@ -131,46 +175,69 @@ def main():
     mu = s.mu_centroid
     lo, hi = mu + w.window[0], mu + w.window[1]
     ctx = Context(s, device=0)
-    p = ctx.params(w.grid, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision=args.precision)
-    ns = ctx.count_states(p)
+    P = lambda prec: ctx.params(w.grid, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision=prec)
+    ns = ctx.count_states(P("fp64"))
     ctx.set_profiling(True)
-    bufs = None
-    print(f"[bench] {w.name} N={w.grid} states={ns}", file=sys.stderr, flush=True)
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    say(f"[bench] {w.name} N={w.grid} states={ns}")
+    bufs = {}
 
-    def step():
-        nonlocal bufs
-        res, bufs = ctx.scattering_rates(p, capacity=ns, buffers=bufs)
-        sig = ctx.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, w.temps, w.grid ** 3)
-        return res, sig
-
-    for i in range(args.warmup):
-        step()
-        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    rates_ms, xform_ms, launches, step_s = [], [], 0, []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        res, sig = step()
+    def timed(prec, warmup, steps):
+        """warmup + steps of one form (rates call + conductivity); per-step
+        wall times, the last call's result and sigma, mean kernel times."""
+        p = P(prec)
+        res = sig = None
+        for i in range(warmup):
+            res, bufs[prec] = ctx.scattering_rates(p, capacity=ns, buffers=bufs.get(prec))
+            ctx.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, w.temps, w.grid ** 3)
+            say(f"[bench] {prec} warmup {i} done")
         torch.cuda.synchronize()
-        step_s.append(time.perf_counter() - ts)
-        st = ctx.stage_times()
-        rates_ms.append(st["rates_ms"])
-        xform_ms.append(st["xform_ms"])
-        launches += st["rates_launches"]
-        print(f"[bench] step {i}: call {st['call_ms']:.1f} ms (tables {st['tables_ms']:.1f}, prep "
-              f"{st['prep_ms']:.1f}, xform {st['xform_ms']:.1f}, rates {st['rates_ms']:.1f})",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / args.steps
+        rates_ms, xform_ms, launches, step_s = [], [], 0, []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ts = time.perf_counter()
+            res, bufs[prec] = ctx.scattering_rates(p, capacity=ns, buffers=bufs.get(prec))
+            sig = ctx.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, w.temps, w.grid ** 3)
+            torch.cuda.synchronize()
+            step_s.append(time.perf_counter() - ts)
+            st = ctx.stage_times()
+            rates_ms.append(st["rates_ms"])
+            xform_ms.append(st["xform_ms"])
+            launches += st["rates_launches"]
+            say(f"[bench] {prec} step {i}: call {st['call_ms']:.1f} ms (tables {st['tables_ms']:.1f}, prep "
+                f"{st['prep_ms']:.1f}, xform {st['xform_ms']:.1f}, rates {st['rates_ms']:.1f})")
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        return dict(t=t, step_s=step_s, res=res, sig=sig, rates_ms=float(np.mean(rates_ms)),
+                    xform_ms=float(np.mean(xform_ms)), launches=launches / steps, st=st)
+
+    # the FP64 path (the reference of the sigma error), then the reduced
+    # forms; the headline is the fastest form within 1e-3 relative sigma
+    # error of the FP64 run, timed for the requested steps
+    side = max(1, min(args.steps, 3))
+    forms = {"fp64": timed("fp64", 1, side)}
+    sig64 = forms["fp64"]["sig"]
+    for prec in ("fp32", "bf16x3"):
+        forms[prec] = timed(prec, 1, side)
+        forms[prec]["sigma_err"] = float(np.max(np.abs(forms[prec]["sig"] - sig64)) / np.max(np.abs(sig64)))
+    forms["fp64"]["sigma_err"] = 0.0
+    ok = [f for f in forms if forms[f]["sigma_err"] <= 1e-3]
+    head = args.precision if args.precision != "auto" else min(ok, key=lambda f: forms[f]["t"])
+    say(f"[bench] headline form {head}: " + ", ".join(f"{f} {forms[f]['t']:.3f} s (sigma err "
+                                                      f"{forms[f]['sigma_err']:.1e})" for f in forms))
+    hd = timed(head, args.warmup, args.steps)
+    sig = hd["sig"]
+    hd["sigma_err"] = float(np.max(np.abs(sig - sig64)) / np.max(np.abs(sig64)))
+    res = hd["res"]
+    t = hd["t"]
     counts = res.counts
     nm, nw = 3 * s.na, s.nw
     box = [len(np.unique(s.rp[:, a])) for a in range(3)]
     flops = rate_kernel_flops(counts, ns, w.grid, box, nm * nw, nm, nw)
-    kern_s = np.mean(rates_ms) / 1e3
-    achieved = flops / kern_s / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    n_launch = launches / args.steps
+    achieved = flops / (hd["rates_ms"] / 1e3) / 1e12
+    peak = PEAK_TFLOPS[head]
+    n_launch = hd["launches"]
+    st = hd["st"]
     out = {
         "metric": METRIC,
         "value": counts["n_kq"] / t,
@@ -180,42 +247,32 @@ def main():
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}[head],
         "data": "synthetic",
         "config": {"workload": w.name, "grid": w.grid, "temps_K": list(w.temps), "eta_eV": w.eta,
-                   "window_eV": [lo, hi], "precision": args.precision, "n_states": ns,
+                   "window_eV": [lo, hi], "precision": head, "n_states": ns,
                    "n_kq": counts["n_kq"], "n_nkq": counts["n_nkq"], "n_terms": counts["n_terms"],
                    "n_vertex": counts["n_vertex"]},
         "sigma_wall_s": t,
-        "ms_per_step_median": float(np.median(step_s)) * 1e3,
+        "sigma_rel_err_vs_fp64": hd["sigma_err"],
+        "ms_per_step_median": float(np.median(hd["step_s"])) * 1e3,
         "sigma_S_per_m_xx": [float(sig[i, 0, 0]) for i in range(sig.shape[0])],
-        "stages_ms": {"tables": st["tables_ms"], "prep": st["prep_ms"], "xform": float(np.mean(xform_ms)),
-                      "rates": float(np.mean(rates_ms)), "call": st["call_ms"]},
+        "stages_ms": {"tables": st["tables_ms"], "prep": st["prep_ms"], "xform": hd["xform_ms"],
+                      "rates": hd["rates_ms"], "call": st["call_ms"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(w.name, args.precision),
+                     "frac": achieved / peak, "traffic": measured_traffic(w.name, head),
                      "kernel": "rates_wave_kernel", "flops_per_step": flops, "launches_per_step": n_launch,
-                     "avg_launch_ms": np.mean(rates_ms) / n_launch, "flops_per_launch": flops / n_launch},
+                     "avg_launch_ms": hd["rates_ms"] / n_launch, "flops_per_launch": flops / n_launch},
+        "forms": {f: {"ms_per_step": forms[f]["t"] * 1e3, "value": forms[f]["res"].counts["n_kq"] / forms[f]["t"],
+                      "speedup_vs_fp64": forms["fp64"]["t"] / forms[f]["t"],
+                      "sigma_rel_err_vs_fp64": forms[f]["sigma_err"], "rates_ms": forms[f]["rates_ms"],
+                      "xform_ms": forms[f]["xform_ms"], "steps": side} for f in forms},
     }
-    if args.precision == "fp64" and args.fp32_form:
-        # the FP32 form on the same workload (same timed protocol), with its
-        # sigma error against this FP64 run: the metric admits forms within
-        # 1e-3 relative sigma error; the headline value above stays FP64
-        p32 = ctx.params(w.grid, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision="fp32")
-        bufs = None
-        res32, bufs = ctx.scattering_rates(p32, capacity=ns, buffers=bufs)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for i in range(args.steps):
-            res32, bufs = ctx.scattering_rates(p32, capacity=ns, buffers=bufs)
-            sig32 = ctx.conductivity(res32.energy, res32.vel, res32.inv_tau.reshape(-1), mu, w.temps, w.grid ** 3)
-        torch.cuda.synchronize()
-        t32 = (time.perf_counter() - t1) / args.steps
-        out["fp32_form"] = {"ms_per_step": t32 * 1e3, "value": res32.counts["n_kq"] / t32,
-                            "speedup_vs_fp64": t / t32,
-                            "sigma_rel_err_vs_fp64": float(np.max(np.abs(sig32 - sig)) / np.max(np.abs(sig)))}
-        print(f"[bench] fp32 form: {t32 * 1e3:.1f} ms per step", file=sys.stderr, flush=True)
+    out["roofline_fp64"] = {"achieved": flops / (forms["fp64"]["rates_ms"] / 1e3) / 1e12, "peak": PEAK_TFLOPS["fp64"],
+                            "frac": flops / (forms["fp64"]["rates_ms"] / 1e3) / 1e12 / PEAK_TFLOPS["fp64"],
+                            "unit": "TFLOP/s"}
     if args.cpu_sample > 0:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        say("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(s, w, mu, lo, hi, res.state_k.cpu().numpy(), args.cpu_sample)
     print(json.dumps(out), flush=True)
     ctx.close()

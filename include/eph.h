@@ -319,6 +319,21 @@ int32_t eph_carrier_density(eph_ctx *ctx, int32_t grid, int32_t band_lo, int32_t
  * [n_temps][3][3].  EPH_E_INVALID when a density is not positive. */
 int32_t eph_mobility(int32_t n_temps, const double *sigma_S_per_m, const double *n_per_m3, double *mobility_cm2);
 
+/* The same SERTA rates (same arguments and outputs as eph_scattering_rates)
+ * computed in the other association of the vertex sum, the k-batch order of
+ * Sec. III.D, kept to measure the comparison of that section on this GPU:
+ * for each batch of q_batch wave vectors q, G_q(Re; nu, i, j) =
+ * sum_{Rp,mu} e^{iq.Rp} g(Re, Rp) u_{mu nu}(q) is formed, then every state
+ * takes sum_Re e^{ik.Re} G_q and the band rotations at each q of the batch.
+ * Its volume per (k,q) pair is N_w^2 N_Re N_nu complex multiply-adds, against
+ * N_w N_nu N_Rp per (n,k,q) of the q-batch order.  FP64 only, on the Rp
+ * boxes the wave kernel serves (EPH_E_UNSUPPORTED otherwise); counts->n_kq
+ * and n_vertex are not counted (0).  With profiling on, eph_stage_times
+ * reports step 1 as ms[2] and step 2 as ms[3], and the number of q batches. */
+int32_t eph_rates_kbatch(eph_ctx *ctx, const eph_rates_params *params, int64_t capacity, int32_t *state_k,
+                         int32_t *state_n, double *energy_eV, double *vel_ms, double *inv_tau_s, eph_counts *counts,
+                         int32_t q_batch);
+
 /* Stage timing.  With profiling on, eph_scattering_rates records HIP events
  * on its stream around its stages; eph_stage_times then returns their GPU
  * durations in milliseconds for the last call:
@@ -341,10 +356,10 @@ int32_t eph_stage_times(const eph_ctx *ctx, double *ms, int64_t *launches);
  * disagree the caller recomputes the rates with eph_scattering_rates
  * (k_subset) and merges them with eph_merge_rates.  This form is not in the
  * paper; it stands beside the SERTA rates of Sec. II.C.
- * Network: features (7) -> 128 -> 128 -> 128 -> n_out, SiLU, FP32; Adam on
+ * Network: features (10) -> 128 -> 128 -> 128 -> n_out, SiLU, FP32; Adam on
  * the mean squared error of normalised log(1/tau); n_out = temperatures.
  * Parameter layout per member (row-major W[out][in]):
- *   W1[128][7] b1[128] W2[128][128] b2 W3[128][128] b3 W4[n_out][128] b4.
+ *   W1[128][10] b1[128] W2[128][128] b2 W3[128][128] b3 W4[n_out][128] b4.
  * All array arguments are DEVICE pointers unless marked host.
  * ------------------------------------------------------------------------ */
 typedef struct eph_mlp eph_mlp;
@@ -360,10 +375,12 @@ void eph_mlp_free(eph_mlp *mlp); /* NULL-safe */
  * in (set = 1). */
 int32_t eph_mlp_params(eph_mlp *mlp, float *host_params, int64_t *n_params, int32_t set);
 
-/* Features x[n][7] = (k1/N, k2/N, k3/N, eps - mu [eV], v [1e6 m/s] x3) of
- * states (state_k, energy_eV, vel_ms as returned by eph_scattering_rates);
- * with inv_tau_s ([n_temps][n]) also the targets y[n][n_temps] =
- * log(inv_tau).  Enqueued on stream. */
+/* Features x[n][10] = (sin 2pi k1/N, cos 2pi k1/N, the same for k2 and k3,
+ * eps - mu [eV], v [1e6 m/s] x3) of states (state_k, energy_eV, vel_ms as
+ * returned by eph_scattering_rates): the reduced k coordinates enter through
+ * periodic functions, as the rates are periodic over the zone.  With
+ * inv_tau_s ([n_temps][n]) also the targets y[n][n_temps] = log(inv_tau).
+ * Enqueued on stream. */
 int32_t eph_mlp_features(eph_ctx *ctx, int64_t n, const int32_t *state_k, const double *energy_eV,
                          const double *vel_ms, int32_t grid, double mu_eV, const double *inv_tau_s,
                          int32_t n_temps, float *x, float *y, void *stream);

@@ -1,6 +1,6 @@
 """FP64 numpy reference of the surrogate MLP (test infrastructure).
 
-Same network and parameter layout as the HIP kernels: 7 -> 128 -> 128 -> 128
+Same network and parameter layout as the HIP kernels: 10 -> 128 -> 128 -> 128
 -> n_out, SiLU after each hidden layer, loss = mean over samples and outputs
 of (prediction - target)^2.  Used to check the GPU forward pass and the
 hand-written backward pass; it is itself pinned against finite differences.
@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import numpy as np
 
-NIN, H = 7, 128
+NIN, H = 10, 128
 
 
 def n_params(nout):

@@ -121,12 +121,13 @@ Workspace plan_workspace(const eph_ctx *c, int N, int precision, int64_t nkl, in
   t += NQ * nw * 8 + NQ * nw * nw * 16 + NQ * nw * 24;              // eps, eigenvectors, velocities
   t += NQ * nm * 8 + NQ * nm * nm * 16;                             // phonon energies, displacements
   if (red) t += NQ * nw * nw * 8 + NQ * nm * nm * 8;                // FP32 rotation tables
+  if (red && wave) t += NQ * (nw + nm) * EPH_MAX_TEMPS * 4;         // FP32 occupation tables
   const size_t ncol = (size_t)c->box.count() * nm * nw, K = (size_t)c->nre * nw;
   if (precision == EPH_FP32) t += ncol * K * 8;                     // FP32 copy of g
   if (precision == EPH_BF16X3) t += 4 * bf16_w_elems(c->nre, c->nw, (int)ncol);  // bf16 hi/lo of g
   if (wave) {
     t += NQ * (nw + nm) * EPH_MAX_TEMPS * 8;                        // occupation tables
-    if ((size_t)N * nw > 512) t += NQ * nw * 4;                     // float energies of long lines
+    t += NQ * nw * 4;                                               // float energies (prefilter)
   } else {
     t += NQ * nw * 10;                                              // energy-sorted lines
   }
@@ -138,6 +139,7 @@ Workspace plan_workspace(const eph_ctx *c, int N, int precision, int64_t nkl, in
   if (gamma) t += NQ * nw * 4 + 16 * nsl;                           // state index table, counts, row starts
   w.fixed = t;
   w.per_state = (size_t)c->box.count() * nm * nw * (red ? 8 : 16);  // X row
+  if (precision == EPH_BF16X3) w.per_state += 4 * bf16_a_elems(c->nre, c->nw);  // bf16 state operand
   return w;
 }
 
@@ -334,7 +336,7 @@ struct GammaReq {
 
 static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
                           int32_t *state_n, double *energy_eV, double *vel_ms, double *inv_tau_s,
-                          eph_counts *counts, bool states_only, GammaReq *gr = nullptr) {
+                          eph_counts *counts, bool states_only, GammaReq *gr = nullptr, int kbatch_q = 0) {
   if (!c) return EPH_E_INVALID;
   c->err.clear();
   if (!p) return fail(c, EPH_E_INVALID, "params is NULL");
@@ -373,6 +375,8 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
   const int gwave = rates_wave_group(nw, nm, c->box, N, p->precision);
   if (gwave == 0 && rates_smem_bytes(p->precision, N, nw, nm, c->box) > 160 * 1024)
     return fail(c, EPH_E_UNSUPPORTED, "Rp box too large for the workgroup rate kernel at this grid");
+  if (kbatch_q > 0 && (gwave == 0 || p->precision != EPH_FP64))
+    return fail(c, EPH_E_UNSUPPORTED, "the k-batch order needs FP64 and a cubic Rp box of edge 4 or 6");
   if (gr && (gwave == 0 || p->precision != EPH_FP64))
     return fail(c, EPH_E_UNSUPPORTED,
                 "transition rates need FP64 and the wave rate kernel (cubic Rp box of edge 4 or 6)");
@@ -492,7 +496,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     EPH_HIP(c, hipMemcpyAsync(&lastpf[0], pos + ns - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     EPH_HIP(c, hipMemcpyAsync(&lastpf[1], flag + ns - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     EPH_HIP(c, hipStreamSynchronize(st));
-    const int64_t ng = lastpf[0] + lastpf[1];
+    int64_t ng = lastpf[0] + lastpf[1];
     EPH_HIP(c, c->grp_start.ensure(sizeof(int64_t) * (ng + 1)));
     int64_t *gstart = c->grp_start.as<int64_t>();
     EPH_HIP(c, launch_group_starts(ns, flag, pos, gstart, st));
@@ -555,7 +559,7 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     a.n_vertex = ctr + 6;
     a.evec32 = fp32 ? c->evec32.as<float2>() : nullptr;
     a.eps32 = nullptr;
-    if (gwave > 0 && N * nw > 512) {  // the wave kernel prefilters long lines from a float copy
+    if (gwave > 0) {  // the wave kernel prefilters from a float copy of the energies
       EPH_HIP(c, c->eps32.ensure(sizeof(float) * NQ * nw));
       EPH_HIP(c, launch_real_to_f32(NQ * nw, c->eps.as<double>(), c->eps32.as<float>(), st));
       a.eps32 = c->eps32.as<float>();
@@ -563,7 +567,59 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
     a.uu32 = fp32 ? c->uu32.as<float2>() : nullptr;
     a.occ_f = c->occ.as<double>();
     a.occ_n = c->occ.as<double>() + (size_t)NQ * nw * EPH_MAX_TEMPS;
+    a.occ32_f = a.occ32_n = nullptr;
+    if (gwave > 0 && fp32) {  // FP32 copies of the occupation tables
+      const size_t no = (size_t)NQ * (nw + nm) * EPH_MAX_TEMPS;
+      EPH_HIP(c, c->occ32.ensure(sizeof(float) * no));
+      EPH_HIP(c, launch_real_to_f32((int64_t)no, c->occ.as<double>(), c->occ32.as<float>(), st));
+      a.occ32_f = c->occ32.as<float>();
+      a.occ32_n = c->occ32.as<float>() + (size_t)NQ * nw * EPH_MAX_TEMPS;
+    }
     const int ncol = c->box.count() * nm * nw;
+    if (kbatch_q > 0) {  // ---- the k-batch order (ablation): q batches, all states each ----
+      const int64_t per_q = (int64_t)c->nre * nm * nw * nw;
+      EPH_HIP(c, c->kb_g.ensure(sizeof(double2) * per_q * kbatch_q));
+      KBatchArgs kb;
+      std::memset(&kb, 0, sizeof(kb));
+      kb.N = N;
+      kb.nw = nw;
+      kb.nm = nm;
+      kb.nt = p->n_temps;
+      kb.nre = c->nre;
+      kb.ns = ns;
+      kb.eta = p->eta_eV;
+      kb.sw = p->sieve_width;
+      kb.wcut = p->omega_cut_eV;
+      kb.pref = a.pref;
+      kb.sk = state_k;
+      kb.sn = state_n;
+      kb.re = c->re.as<int>();
+      kb.eps = c->eps.as<double>();
+      kb.om = c->om.as<double>();
+      kb.evec = c->evec.as<double2>();
+      kb.tab = c->tab.as<double2>();
+      kb.Gq = c->kb_g.as<double2>();
+      kb.occ_f = a.occ_f;
+      kb.occ_n = a.occ_n;
+      kb.inv_tau = inv_tau_s;
+      kb.st_counts = c->state_cnt.as<int64_t>();
+      for (int64_t q0 = 0; q0 < NQ; q0 += kbatch_q) {
+        const int nb = (int)std::min<int64_t>(kbatch_q, NQ - q0);
+        int eb0, eb1, eb2;
+        EPH_HIP(c, tm.mark(&eb0));
+        EPH_HIP(c, launch_kbatch_step1(q0, nb, N, c->box, c->nre, nm, nw, ncol, c->wt64.as<double2>(),
+                                       c->uu.as<double2>(), c->tab.as<double2>(), c->kb_g.as<double2>(), st));
+        EPH_HIP(c, tm.mark(&eb1));
+        kb.q0 = q0;
+        kb.nb = nb;
+        EPH_HIP(c, launch_kbatch_step2(kb, st));
+        EPH_HIP(c, tm.mark(&eb2));
+        e_batch.insert(e_batch.end(), {eb0, eb1, eb2});
+        c->launches[0]++;
+        c->launches[1]++;
+      }
+      ng = 0;  // the q-batch loop below has nothing left to do
+    }
     // ---- transition rates: count pass, row starts, placement ----
     std::unique_ptr<eph_gamma> gam;
     std::vector<int64_t> hrow;
@@ -660,11 +716,12 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
         g1++;
       const int64_t sa = hg[g0], sb = hg[g1];
       EPH_HIP(c, c->xbuf.ensure(xrow * (size_t)(sb - sa)));
+      if (p->precision == EPH_BF16X3) EPH_HIP(c, c->abf.ensure(4 * bf16_a_elems(c->nre, nw) * (size_t)(sb - sa)));
       int eb0, eb1, eb2;
       EPH_HIP(c, tm.mark(&eb0));
       if (p->precision == EPH_BF16X3)
         EPH_HIP(c, launch_xform_bf16x3(sb - sa, state_k + sa, state_n + sa, N, nw, c->nre, c->re.as<int>(), ncol,
-                                       c->wtbf.p, c->evec.as<double2>(), c->tab.as<double2>(),
+                                       c->wtbf.p, c->abf.p, c->evec.as<double2>(), c->tab.as<double2>(),
                                        c->xbuf.as<float2>(), st));
       else if (fp32)
         EPH_HIP(c, launch_xform32(sb - sa, state_k + sa, state_n + sa, N, nw, c->nre, c->re.as<int>(), ncol,
@@ -769,6 +826,13 @@ int32_t eph_scattering_rates(eph_ctx *c, const eph_rates_params *p, int64_t capa
 int32_t eph_select_states(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,
                           int32_t *state_n, double *energy_eV, double *vel_ms, eph_counts *counts) {
   return rates_impl(c, p, capacity, state_k, state_n, energy_eV, vel_ms, nullptr, counts, true);
+}
+
+int32_t eph_rates_kbatch(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k, int32_t *state_n,
+                         double *energy_eV, double *vel_ms, double *inv_tau_s, eph_counts *counts, int32_t q_batch) {
+  if (!c) return EPH_E_INVALID;
+  if (q_batch < 1 || q_batch > (1 << 20)) return fail(c, EPH_E_INVALID, "q_batch must be 1 .. 2^20");
+  return rates_impl(c, p, capacity, state_k, state_n, energy_eV, vel_ms, inv_tau_s, counts, false, nullptr, q_batch);
 }
 
 int32_t eph_gamma_estimate(eph_ctx *c, const eph_rates_params *p, int64_t capacity, int32_t *state_k,

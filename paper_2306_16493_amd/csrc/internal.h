@@ -88,6 +88,7 @@ struct eph_ctx {
   eph::DevBuf grp_start, grp_tmp;
   eph::DevBuf line_e, line_key;         // energy-sorted p-lines
   eph::DevBuf xbuf;                     // X_s = Re transform + j rotation
+  eph::DevBuf abf;                      // bf16 hi/lo state operand of the BF16x3 Re transform
   eph::DevBuf counters;                 // int64 counters
   eph::DevBuf sig_part;                 // sigma partial sums
   double *scratch = nullptr;            // device address of the static workspace (eph_conductivity_noalloc)
@@ -96,7 +97,9 @@ struct eph_ctx {
   eph::DevBuf gcur;                     // per-state transition-rate counts / cursors
   eph::DevBuf gstage_col, gstage_val;   // staging of spilled transition rates
   eph::DevBuf bte_f;                    // F0, F, F' of the iteration
+  eph::DevBuf kb_g;                     // G_q of a q batch (k-batch order)
   eph::DevBuf occ;                      // Fermi and Bose factor tables
+  eph::DevBuf occ32;                    // their FP32 copies (reduced-precision forms)
   // stage timing
   bool profiling = false;
   std::vector<hipEvent_t> ev;  // created on demand, reused across calls
@@ -173,9 +176,12 @@ hipError_t launch_real_to_f32(int64_t n, const double *in, float *out, hipStream
 hipError_t launch_to_f32(int64_t n, const double2 *in, float2 *out, hipStream_t st);
 // bf16 hi/lo split of the g operand in real form (2 * bf16_w_elems bf16 values)
 size_t bf16_w_elems(int nre, int nw, int ncol);
+// bf16 values per state of one half (hi or lo) of the state-side operand
+size_t bf16_a_elems(int nre, int nw);
 hipError_t launch_split_bf16(int nre, int nw, int ncol, const double2 *wt, void *out, hipStream_t st);
+// abf: workspace of 2 * ns * bf16_a_elems bf16 values (the state operand, hi and lo)
 hipError_t launch_xform_bf16x3(int64_t ns, const int32_t *sk, const int32_t *sn, int N, int nw, int nre,
-                               const int *re, int ncol, const void *wbf, const double2 *evec,
+                               const int *re, int ncol, const void *wbf, void *abf, const double2 *evec,
                                const double2 *tab, float2 *X, hipStream_t st);
 
 struct RatesArgs {
@@ -205,6 +211,7 @@ struct RatesArgs {
   unsigned long long *n_vertex;
   const double *occ_f;             // [N^3][nw][EPH_MAX_TEMPS] Fermi factors (wave kernel)
   const double *occ_n;             // [N^3][nm][EPH_MAX_TEMPS] Bose factors, 0 below omega_cut
+  const float *occ32_f, *occ32_n;  // FP32 copies of occ_f, occ_n (reduced-precision forms)
   int q3_lo, q3_hi;                // q3 planes of this launch (wave kernel)
   int q3_cur;                      // the plane (wave kernel launches one plane at a time)
   // transition rates of the iterative BTE (wave kernel, FP64, count and emit modes)
@@ -222,6 +229,23 @@ hipError_t launch_rates(int precision, const RatesArgs &a, hipStream_t st);
 // (0 when the shape is not served and launch_rates must be used).
 int rates_wave_group(int nw, int nm, RpBox box, int N, int precision);
 hipError_t launch_rates_wave(int precision, const RatesArgs &a, hipStream_t st, int mode = kRates);
+// k-batch order of the vertex (k_kbatch.hip): step 1 forms G_q for a batch
+// of q, step 2 runs one wave per state over that batch.
+struct KBatchArgs {
+  int N, nw, nm, nt, nre, nb;
+  int64_t q0, ns;
+  double eta, sw, wcut, pref;
+  const int32_t *sk, *sn;
+  const int *re;
+  const double *eps, *om;
+  const double2 *evec, *tab, *Gq;
+  const double *occ_f, *occ_n;
+  double *inv_tau;
+  int64_t *st_counts;
+};
+hipError_t launch_kbatch_step1(int64_t q0, int nb, int N, RpBox box, int nre, int nm, int nw, int ncol,
+                               const double2 *wt, const double2 *uu, const double2 *tab, double2 *Gq, hipStream_t st);
+hipError_t launch_kbatch_step2(const KBatchArgs &a, hipStream_t st);
 // Occupation tables: occ_f[k][n][t] = 1/(exp((eps-mu)/kT_t)+1),
 // occ_n[q][nu][t] = 1/expm1(hbar w/kT_t) (0 when hbar w < wcut).
 hipError_t launch_occupations(int64_t nq, int nw, int nm, const double *eps, const double *om, double mu,

@@ -23,7 +23,7 @@
 namespace eph {
 namespace mlp {
 
-constexpr int NIN = 7;
+constexpr int NIN = 10;  // features: (sin, cos)(2 pi k_i/N) x 3, eps - mu, v x 3
 constexpr int H = 128;
 constexpr int TS = 32;       // samples per workgroup tile
 constexpr int THREADS = 256;
@@ -286,7 +286,9 @@ __global__ __launch_bounds__(THREADS) void mlp_forward_kernel(int nout, int64_t 
   }
 }
 
-// Features (k reduced, eps - mu, v / 1e6 m/s) and log-rate targets.
+// Features (the reduced k coordinates as (sin, cos)(2 pi k_i / N), which are
+// periodic over the zone like the rates themselves, eps - mu, v / 1e6 m/s)
+// and log-rate targets.
 __global__ void mlp_features_kernel(int64_t n, const int32_t *__restrict__ sk, const double *__restrict__ e,
                                     const double *__restrict__ v, int N, double mu,
                                     const double *__restrict__ inv_tau, int nt, float *__restrict__ x,
@@ -294,11 +296,15 @@ __global__ void mlp_features_kernel(int64_t n, const int32_t *__restrict__ sk, c
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int64_t k = sk[s];
-  x[s * NIN + 0] = (float)((double)(k % N) / N);
-  x[s * NIN + 1] = (float)((double)((k / N) % N) / N);
-  x[s * NIN + 2] = (float)((double)(k / ((int64_t)N * N)) / N);
-  x[s * NIN + 3] = (float)(e[s] - mu);
-  for (int a = 0; a < 3; a++) x[s * NIN + 4 + a] = (float)(v[3 * s + a] * 1e-6);
+  const int64_t kc[3] = {k % N, (k / N) % N, k / ((int64_t)N * N)};
+  for (int a = 0; a < 3; a++) {
+    double sn_, cs_;
+    sincospi(2.0 * (double)kc[a] / N, &sn_, &cs_);
+    x[s * NIN + 2 * a] = (float)sn_;
+    x[s * NIN + 2 * a + 1] = (float)cs_;
+  }
+  x[s * NIN + 6] = (float)(e[s] - mu);
+  for (int a = 0; a < 3; a++) x[s * NIN + 7 + a] = (float)(v[3 * s + a] * 1e-6);
   if (inv_tau && y)
     for (int t = 0; t < nt; t++) y[s * nt + t] = (float)log(fmax(inv_tau[(int64_t)t * n + s], 1e-300));
 }

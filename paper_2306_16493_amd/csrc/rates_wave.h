@@ -34,11 +34,22 @@
 namespace eph {
 namespace wave {
 
+// Waves per workgroup: 4 (they share the phase table and, working on
+// consecutive groups of one k-line, their L1), 2 for the FP64 form of 48
+// channels, whose per-wave LDS would otherwise let only one workgroup of 4
+// onto a CU.
+template <class T, int NW, int NM>
+__host__ __device__ constexpr int waves_per_block() {
+  return (NW * NM >= 48 && sizeof(T) == 8) ? 2 : 4;
+}
+
 template <class T, int NW, int NM, int GW, int NB, class LT = double>
 struct WaveLayout {
   static constexpr int C = NW * NM;
   static constexpr int SMX = GW + NW;  // member states + shadow states
-  static constexpr int NZ = 4;         // Z ring slots (q-lines in flight)
+  // Z ring slots (q-lines in flight): 4, or 2 for 48 channels (LDS)
+  static constexpr int NZ = C >= 48 ? 2 : 4;
+  static constexpr int WPB = waves_per_block<T, NW, NM>();
   static constexpr int VCAP = 64 + 64 * GW * NW;  // vertex queue: one pass of candidates + a partial pass
   // one Z block per (slot, state), padded by 16 bytes so that the blocks a
   // vertex pass reads at the same offset fall in different LDS banks
@@ -53,28 +64,42 @@ struct WaveLayout {
     return z_bytes() + q_bytes(N) + misc_bytes() + line_bytes(N) + v_bytes();
   }
   __host__ __device__ static size_t tab_bytes(int N) { return align16(sizeof(typename V2<T>::t) * N); }
-  __host__ __device__ static size_t total(int N) { return tab_bytes(N) + 4 * per_wave(N); }
+  __host__ __device__ static size_t total(int N) { return tab_bytes(N) + WPB * per_wave(N); }
 };
 
-#ifndef EPH_WAVE_OCC
-#define EPH_WAVE_OCC 2
-#endif
+// Waves per SIMD the register allocation targets: 3 for the FP32 form of up
+// to 24 channels (whose LDS then also admits three workgroups per CU), 2
+// otherwise.
+template <class T, int NW, int NM>
+__host__ __device__ constexpr int waves_per_eu() {
+  return (sizeof(T) == 4 && NW * NM <= 24) ? 3 : 2;
+}
 // MODE: kRates computes 1/tau; kCount only counts, per state, the transition
 // rates to final states in the state list (no transforms, no vertices);
 // kEmit computes 1/tau and also writes those transition rates (the summed
 // terms of each (state, q, m) vertex) at the state's running cursor.
 template <class T, int NW, int NM, int GW, int NB, int LPL, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OCC))) void rates_wave_kernel(
-    RatesArgs a) {
+__global__ __launch_bounds__((waves_per_block<T, NW, NM>() * 64))
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<T, NW, NM>())))
+void rates_wave_kernel(RatesArgs a) {
   using C2 = typename V2<T>::t;
-  // long lines keep a float copy of their energies for the prefilter, so
-  // that two workgroups still fit a CU's LDS
-  using LT = typename std::conditional<(LPL >= 16), float, double>::type;
+  // the prefilter reads a float copy of the final-state energies (half the
+  // LDS and prefetch registers of an FP64 copy); its window is widened to
+  // cover the rounding, and the exact sieve that follows is FP64
+  using LT = float;
   using LY = WaveLayout<T, NW, NM, GW, NB, LT>;
   constexpr int C = NW * NM;
   constexpr int SMX = LY::SMX;
   constexpr int NZ = LY::NZ;
   constexpr int NPAIR = (GW * NB * C + 63) / 64;
+  constexpr int WPB = LY::WPB;
+  // lanes per vertex: with 8 orbitals and 6 modes a vertex is split over two
+  // lanes (each contracts half of the orbitals, the halves are added, and
+  // each rotates onto half of the modes), which keeps the kernel within its
+  // registers next to Y
+  constexpr int VL = (NW == 8 && NM == 6) ? 2 : 1;
+  constexpr int NWL = NW / VL;  // orbitals per lane in the W contraction
+  constexpr int NML = NM / VL;  // modes per lane in the rotation
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = a.N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -94,15 +119,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   LT *sLine = reinterpret_cast<LT *>(misc + LY::misc_bytes());  // [NW][N] current line energies
   uint2 *sV = reinterpret_cast<uint2 *>(misc + LY::misc_bytes() + LY::line_bytes(N));  // vertex queue
 
-  for (int t = threadIdx.x; t < N; t += 256) sTab[t] = mk<T>((T)a.tab[t].x, (T)a.tab[t].y);
+  for (int t = threadIdx.x; t < N; t += WPB * 64) sTab[t] = mk<T>((T)a.tab[t].x, (T)a.tab[t].y);
   __syncthreads();  // the only workgroup barrier
 
   // XCD-aware block order: consecutive block indices go round-robin to the
   // 8 XCDs, so give each XCD a contiguous range of groups.
-  const int64_t nblk = (a.ng + 3) / 4;
+  const int64_t nblk = (a.ng + WPB - 1) / WPB;
   const int64_t per_xcd = (nblk + 7) / 8;
   const int64_t blk = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  const int64_t g = blk * 4 + wave;
+  const int64_t g = blk * WPB + wave;
   if (blk >= nblk || g >= a.ng) return;  // wave-uniform
 
   const int64_t s0 = a.gstart[g];
@@ -118,7 +143,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   const int k2 = (int)((kfirst / N) % N), k3 = (int)(kfirst / ((int64_t)N * N));
   // prefilter window (a float line copy is within 1e-4 eV of the FP64
   // values for |eps| < 1000 eV; the exact sieve that follows uses FP64)
-  const double W = a.wmax + a.sw * a.eta + (sizeof(LT) == 4 ? 1e-4 : 0.0);
+  // (a float copy is within 1e-4 eV of the FP64 values for |eps| < 1000 eV)
+  const double W = a.wmax + a.sw * a.eta + 1e-4;
   const double cut = a.sw * a.eta;
   const double inv_eta = 1.0 / a.eta;
   const double dnorm = 1.0 / (1.7724538509055160273 * a.eta);
@@ -181,8 +207,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   constexpr int LPR = PF ? LPL : 1;
   LT nxt[LPR];
   const LT *eline;  // energy table the prefilter reads (FP64, or its float copy for long lines)
-  if constexpr (sizeof(LT) == 4) eline = a.eps32;
-  else eline = a.eps;
+  eline = a.eps32;
   {
     const int l3 = (k3 + a.q3_lo >= N) ? k3 + a.q3_lo - N : k3 + a.q3_lo;
     const LT *l0 = eline + (size_t)(k2 + N * l3) * LN;
@@ -202,10 +227,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
   // vm << 12 | q2 << 18.
   int vn = 0;
   auto vdrain = [&](int count) __attribute__((always_inline)) {
-    for (int base = 0; base < count; base += 64) {
-      const int i = base + lane;
-      if constexpr (MODE == kCount) {
-        // only which final states the kept vertices reach
+    if constexpr (MODE == kCount) {
+      // only which final states the kept vertices reach
+      for (int base = 0; base < count; base += 64) {
+        const int i = base + lane;
         if (i < count) {
           const uint2 it = sV[i];
           const int p1 = (int)(it.x & 1023u), s = (int)(it.y & 7u), m = (int)((it.y >> 3) & 7u);
@@ -217,8 +242,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 #pragma unroll
           for (int ss = 0; ss < GW; ss++) gcur[ss] += (in_list && ss == s) ? 1 : 0;
         }
-        continue;
       }
+      return;
+    }
+    const int h = (VL == 1) ? 0 : (lane & (VL - 1));  // this lane's half of a vertex
+    for (int base = 0; base < count; base += 64 / VL) {
+      const int i = base + lane / VL;
       int e_state = -1, e_col = -1;  // transition rate of this lane's vertex (kEmit)
       double e_val[EPH_MAX_TEMPS];
       if (i < count) {
@@ -237,15 +266,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 #pragma unroll
       for (int ss = 1; ss < GW; ss++) es = (s == ss) ? esm[ss] : es;
       const double epm = a.eps[pidx * NW + m];
-      double omq[NM];
+      double omq[NML];  // phonon energies of this lane's modes
 #pragma unroll
-      for (int nu = 0; nu < NM; nu++) omq[nu] = a.om[qidx * NM + nu];
-      my_nv++;
-      C2 vrow[NW];
+      for (int nl = 0; nl < NML; nl++) omq[nl] = a.om[qidx * NM + h * NML + nl];
+      my_nv += (h == 0) ? 1 : 0;
+      C2 vrow[NWL];
 #pragma unroll
-      for (int i2 = 0; i2 < NW; i2++) {
-        if constexpr (sizeof(T) == 8) vrow[i2] = a.evec[(pidx * NW + m) * NW + i2];
-        else vrow[i2] = a.evec32[(pidx * NW + m) * NW + i2];
+      for (int j = 0; j < NWL; j++) {
+        if constexpr (sizeof(T) == 8) vrow[j] = a.evec[(pidx * NW + m) * NW + h * NWL + j];
+        else vrow[j] = a.evec32[(pidx * NW + m) * NW + h * NWL + j];
       }
       T wr[NM], wi[NM];
 #pragma unroll
@@ -254,20 +283,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
       // two table entries (per-lane table lookups would conflict in LDS banks)
       C2 ph = sTab[i1];
       const C2 rq = sTab[q1];
-      const C2 *zs = sZ + ((size_t)zs_slot * GW + s) * LY::ZB;
+      const C2 *zs = sZ + ((size_t)zs_slot * GW + s) * LY::ZB + h * NWL;
 #pragma unroll 1
       for (int pp = 0; pp < NB; pp++) {
 #pragma unroll
         for (int mu = 0; mu < NM; mu++) {
           T tr = 0, ti = 0;
 #pragma unroll
-          for (int i2 = 0; i2 < NW; i2++) {
-            const C2 z = zs[pp * C + mu * NW + i2];
-            cmac_conj<T>(tr, ti, vrow[i2].x, vrow[i2].y, z.x, z.y);
+          for (int j = 0; j < NWL; j++) {
+            const C2 z = zs[pp * C + mu * NW + j];
+            cmac_conj<T>(tr, ti, vrow[j].x, vrow[j].y, z.x, z.y);
           }
           cmac<T>(wr[mu], wi[mu], ph.x, ph.y, tr, ti);
         }
         ph = mk<T>(fma(ph.x, rq.x, -ph.y * rq.y), fma(ph.x, rq.y, ph.y * rq.x));
+      }
+      if constexpr (VL == 2) {  // the two halves of the orbital sum (both lanes share i)
+#pragma unroll
+        for (int mu = 0; mu < NM; mu++) {
+          wr[mu] += __shfl_xor(wr[mu], 1, 64);
+          wi[mu] += __shfl_xor(wi[mu], 1, 64);
+        }
       }
       double contrib[EPH_MAX_TEMPS];
       if constexpr (sizeof(T) == 8) {
@@ -280,7 +316,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 #pragma unroll
         for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = 0.0;
 #pragma unroll
-        for (int nu = 0; nu < NM; nu++) {
+        for (int nl = 0; nl < NML; nl++) {
+          const int nu = h * NML + nl;
           const bool okp = (vp >> nu) & 1u, okm = (vm >> nu) & 1u;
           if (!(okp || okm)) continue;
           T gr = 0, gi = 0;
@@ -290,7 +327,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
             cmac<T>(gr, gi, wr[mu], wi[mu], u.x, u.y);
           }
           const double g2 = fma((double)gr, (double)gr, (double)gi * (double)gi);
-          const double xp = es + omq[nu] - epm, xm = es - omq[nu] - epm;
+          const double xp = es + omq[nl] - epm, xm = es - omq[nl] - epm;
           const double dp = okp ? exp(-(xp * inv_eta) * (xp * inv_eta)) * dnorm : 0.0;
           const double dm = okm ? exp(-(xm * inv_eta) * (xm * inv_eta)) * dnorm : 0.0;
 #pragma unroll
@@ -300,53 +337,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
           }
         }
       } else {
-        // FP32: the q-side data of every mode and the Fermi factors, in one
-        // batch of loads (occupation rows are padded to EPH_MAX_TEMPS; padding is never
-        // accumulated into a written rate)
-        static_assert(EPH_MAX_TEMPS == 4, "occupation rows are read as two double2");
-        C2 uq[NM][NM];
-        double nqv[NM][EPH_MAX_TEMPS], fo[EPH_MAX_TEMPS];
+        // FP32 form: the q-side data of this lane's modes and the Fermi
+        // factors in one batch of loads from FP32 copies of the tables, and
+        // |g|^2, the Gaussians and the occupation weights in FP32 (the
+        // arguments x are formed in FP64 from the FP64 energies); the
+        // vertex's contribution is then accumulated in FP64 (occupation rows
+        // are padded to EPH_MAX_TEMPS; padding is never accumulated into a
+        // written rate)
+        static_assert(EPH_MAX_TEMPS == 4, "occupation rows are read as one float4");
+        C2 uq[NML][NM];
+        float4 nqv[NML];
 #pragma unroll
-        for (int nu = 0; nu < NM; nu++)
+        for (int nl = 0; nl < NML; nl++)
 #pragma unroll
-          for (int mu = 0; mu < NM; mu++) {
-            uq[nu][mu] = a.uu32[(qidx * NM + nu) * NM + mu];
-          }
+          for (int mu = 0; mu < NM; mu++) uq[nl][mu] = a.uu32[(qidx * NM + h * NML + nl) * NM + mu];
 #pragma unroll
-        for (int nu = 0; nu < NM; nu++) {
-          const double2 *r = reinterpret_cast<const double2 *>(a.occ_n + (qidx * NM + nu) * EPH_MAX_TEMPS);
-          const double2 r0 = r[0], r1 = r[1];
-          nqv[nu][0] = r0.x;
-          nqv[nu][1] = r0.y;
-          nqv[nu][2] = r1.x;
-          nqv[nu][3] = r1.y;
-        }
-        {
-          const double2 *r = reinterpret_cast<const double2 *>(a.occ_f + (pidx * NW + m) * EPH_MAX_TEMPS);
-          const double2 r0 = r[0], r1 = r[1];
-          fo[0] = r0.x;
-          fo[1] = r0.y;
-          fo[2] = r1.x;
-          fo[3] = r1.y;
-        }
-#pragma unroll
-        for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = 0.0;
+        for (int nl = 0; nl < NML; nl++)
+          nqv[nl] = reinterpret_cast<const float4 *>(a.occ32_n)[qidx * NM + h * NML + nl];
+        const float4 fo = reinterpret_cast<const float4 *>(a.occ32_f)[pidx * NW + m];
+        const float ie = (float)inv_eta, dn = (float)dnorm;
+        float cf[EPH_MAX_TEMPS] = {0.f, 0.f, 0.f, 0.f};
         // every mode is evaluated and masked (about 5 of the 6 (nu, +-) terms
         // of a vertex are kept, so branching would not save work)
 #pragma unroll
-        for (int nu = 0; nu < NM; nu++) {
+        for (int nl = 0; nl < NML; nl++) {
+          const int nu = h * NML + nl;
           const bool okp = (vp >> nu) & 1u, okm = (vm >> nu) & 1u;
           T gr = 0, gi = 0;
 #pragma unroll
-          for (int mu = 0; mu < NM; mu++) cmac<T>(gr, gi, wr[mu], wi[mu], uq[nu][mu].x, uq[nu][mu].y);
-          const double g2 = fma((double)gr, (double)gr, (double)gi * (double)gi);
-          const double xp = es + omq[nu] - epm, xm = es - omq[nu] - epm;
-          const double ep = exp(-(xp * inv_eta) * (xp * inv_eta)), em = exp(-(xm * inv_eta) * (xm * inv_eta));
-          const double dp = okp ? ep * dnorm : 0.0, dm = okm ? em * dnorm : 0.0;
+          for (int mu = 0; mu < NM; mu++) cmac<T>(gr, gi, wr[mu], wi[mu], uq[nl][mu].x, uq[nl][mu].y);
+          const float g2 = fmaf(gr, gr, gi * gi);
+          const float xp = (float)(es + omq[nl] - epm) * ie, xm = (float)(es - omq[nl] - epm) * ie;
+          const float dp = okp ? __expf(-xp * xp) * dn : 0.f, dm = okm ? __expf(-xm * xm) * dn : 0.f;
+          const float nq[EPH_MAX_TEMPS] = {nqv[nl].x, nqv[nl].y, nqv[nl].z, nqv[nl].w};
+          const float ff[EPH_MAX_TEMPS] = {fo.x, fo.y, fo.z, fo.w};
 #pragma unroll
           for (int t = 0; t < EPH_MAX_TEMPS; t++)
-            contrib[t] = fma(g2, fma(nqv[nu][t] + fo[t], dp, (1.0 + nqv[nu][t] - fo[t]) * dm), contrib[t]);
+            cf[t] = fmaf(g2, fmaf(nq[t] + ff[t], dp, (1.f + nq[t] - ff[t]) * dm), cf[t]);
         }
+#pragma unroll
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) contrib[t] = (double)cf[t];
       }
 #pragma unroll
       for (int ss = 0; ss < GW; ss++) {
@@ -355,10 +385,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
         for (int t = 0; t < EPH_MAX_TEMPS; t++) acc[ss][t] += me ? contrib[t] : 0.0;
       }
       if constexpr (MODE == kEmit) {
-        e_col = a.stidx[pidx * NW + m];
-        e_state = s;
+        // the vertex's transition rate: both halves' modes, emitted by lane half 0
 #pragma unroll
-        for (int t = 0; t < EPH_MAX_TEMPS; t++) e_val[t] = a.pref * contrib[t];
+        for (int t = 0; t < EPH_MAX_TEMPS; t++) {
+          double v = contrib[t];
+          if constexpr (VL == 2) v += __shfl_xor(v, 1, 64);
+          e_val[t] = a.pref * v;
+        }
+        e_col = (h == 0) ? a.stidx[pidx * NW + m] : -1;
+        e_state = s;
       }
       }
       if constexpr (MODE == kEmit) {
@@ -480,21 +515,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 #pragma unroll
       for (int p2 = 0; p2 < NB; p2++) yr[j][p2] = yi[j][p2] = 0;
     if constexpr (MODE != kCount) {
-      int i3 = imod(q3 * lo3, N);
-#pragma unroll 1
-      for (int p3 = 0; p3 < NB; p3++) {
-        const C2 ph = sTab[i3];
-        i3 += q3;
-        i3 -= (i3 >= N) ? N : 0;
+      // one pair slot at a time, p3 rolled: at most NB loads of X in flight,
+      // so the loads do not compete with Y for registers
 #pragma unroll
-        for (int j = 0; j < NPAIR; j++) {
-          const int P = lane + 64 * j;
-          const int s = P / (NB * C), p1 = (P / C) % NB, c = P % C;
-          if (s < S) {
-            const C2 *xs = Xg + (s0 + s - a.s_base) * xrow + (int64_t)p1 * NB * NB * C + p3 * C + c;
+      for (int j = 0; j < NPAIR; j++) {
+        const int P = lane + 64 * j;
+        const int s = P / (NB * C), p1 = (P / C) % NB, c = P % C;
+        if (s < S) {
+          const C2 *xs = Xg + (s0 + s - a.s_base) * xrow + (int64_t)p1 * NB * NB * C + c;
+          int i3 = imod(q3 * lo3, N);
+#pragma unroll 1
+          for (int p3 = 0; p3 < NB; p3++) {
+            const C2 ph = sTab[i3];
+            i3 += q3;
+            i3 -= (i3 >= N) ? N : 0;
 #pragma unroll
             for (int p2 = 0; p2 < NB; p2++) {
-              const C2 x = xs[p2 * NB * C];
+              const C2 x = xs[p2 * NB * C + p3 * C];
               cmac<T>(yr[j][p2], yi[j][p2], ph.x, ph.y, x.x, x.y);
             }
           }
@@ -566,22 +603,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
       }
       __syncwarp();
       // ---- candidates of this q-line: (k-slot, p1) with some band in the window ----
+      // The states of one k point come in band order, so their energies
+      // ascend; a final band within W of any of them lies in [e_first - W,
+      // e_last + W], which is tested in float (a superset of the exact
+      // test, which the FP64 sieve then makes).
       for (int ks = 0; ks < NK; ks++) {
         const int sf = sKfirst[ks], sc = sKcnt[ks];
-        double esr[NW];  // energies of the k-slot's states; unused slots never match
-#pragma unroll
-        for (int j = 0; j < NW; j++) esr[j] = (j < sc) ? sEps[sf + j] : 1e300;
+        const float lo_w = (float)(sEps[sf] - W), hi_w = (float)(sEps[sf + sc - 1] + W);
         for (int c0 = 0; c0 < N; c0 += 64) {
           const int p1 = c0 + lane;
           bool any = false;
           if (p1 < N) {
-            double ev[NW];
 #pragma unroll
-            for (int m = 0; m < NW; m++) ev[m] = (double)sLine[m * N + p1];
-#pragma unroll
-            for (int m = 0; m < NW; m++)
-#pragma unroll
-              for (int j = 0; j < NW; j++) any |= fabs(ev[m] - esr[j]) <= W;
+            for (int m = 0; m < NW; m++) {
+              const float ev = sLine[m * N + p1];
+              any |= (ev >= lo_w) & (ev <= hi_w);
+            }
           }
           const unsigned long long bits = __ballot(any);
           if (any) sQ[qn + __popcll(bits & ((1ull << lane) - 1ull))] =
@@ -671,15 +708,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EPH_WAVE_OC
 
 template <class T, int NW, int NM, int GW, int NB, int LPL, int MODE>
 hipError_t launch_wave_l(const RatesArgs &a, hipStream_t st) {
-  using LY = WaveLayout<T, NW, NM, GW, NB, typename std::conditional<(LPL >= 16), float, double>::type>;
+  using LY = WaveLayout<T, NW, NM, GW, NB, float>;
   const size_t sh = LY::total(a.N);
   if (sh > 160 * 1024) return hipErrorInvalidValue;
   auto kern = rates_wave_kernel<T, NW, NM, GW, NB, LPL, MODE>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  const int64_t nblk = (a.ng + 3) / 4;
+  const int64_t nblk = (a.ng + LY::WPB - 1) / LY::WPB;
   const int64_t grid = ((nblk + 7) / 8) * 8;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), sh, st, a);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(LY::WPB * 64), sh, st, a);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ EPH_OK, EPH_E_INVALID, EPH_E_NOMEM, EPH_E_DEVICE, EPH_E_STATE, EPH_E_TRUNCATED, 
 EPH_FP64, EPH_FP32, EPH_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": EPH_FP64, "fp32": EPH_FP32, "bf16x3": EPH_BF16X3}
 MAX_TEMPS = 4
+MLP_FEATURES = 10  # inputs of the surrogate network (include/eph.h)
 
 # every symbol declared in include/eph.h
 EXPORTS = ("eph_load_wannier", "eph_free", "eph_last_error", "eph_scattering_rates", "eph_select_states",
@@ -28,7 +29,7 @@ EXPORTS = ("eph_load_wannier", "eph_free", "eph_last_error", "eph_scattering_rat
            "eph_set_profiling", "eph_stage_times", "eph_mlp_create", "eph_mlp_free", "eph_mlp_params",
            "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient", "eph_mlp_predict", "eph_mlp_blend",
            "eph_merge_rates", "eph_gamma_estimate", "eph_rates_gamma", "eph_gamma_info", "eph_gamma_copy",
-           "eph_gamma_free", "eph_bte_iterate")
+           "eph_gamma_free", "eph_bte_iterate", "eph_rates_kbatch")
 
 
 class EphError(RuntimeError):
@@ -118,7 +119,9 @@ def lib():
         L.eph_gamma_free.argtypes = [vp]
         L.eph_gamma_free.restype = None
         L.eph_bte_iterate.argtypes = [vp, vp, vp, vp, vp, i64, i32, f64, vp, vp, C.POINTER(i32), vp]
-        for f in ("eph_gamma_estimate", "eph_rates_gamma", "eph_gamma_info", "eph_gamma_copy", "eph_bte_iterate"):
+        L.eph_rates_kbatch.argtypes = [vp, C.POINTER(RatesParams), i64, vp, vp, vp, vp, vp, C.POINTER(Counts), i32]
+        for f in ("eph_gamma_estimate", "eph_rates_gamma", "eph_gamma_info", "eph_gamma_copy", "eph_bte_iterate",
+                  "eph_rates_kbatch"):
             getattr(L, f).restype = C.c_int32
         for f in ("eph_mlp_create", "eph_mlp_params", "eph_mlp_features", "eph_mlp_train", "eph_mlp_gradient",
                   "eph_mlp_predict", "eph_mlp_blend", "eph_merge_rates", "eph_transport", "eph_carrier_density",
@@ -402,6 +405,26 @@ class _Bte:
                           bufs["it"][:nt * ns].view(nt, ns), cnt.as_dict())
         return res, Gamma(self, h)
 
+    def rates_kbatch(self, params, q_batch=256, buffers=None):
+        """eph_rates_kbatch: the rates in the k-batch order (RatesResult, buffers)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        ns = self.count_states(params)
+        nt = int(params.n_temps)
+        cap = max(ns, 1)
+        if buffers is None:
+            buffers = dict(k=torch.empty(cap, dtype=torch.int32, device=dev),
+                           n=torch.empty(cap, dtype=torch.int32, device=dev),
+                           e=torch.empty(cap, dtype=torch.float64, device=dev),
+                           v=torch.empty(cap, 3, dtype=torch.float64, device=dev),
+                           it=torch.empty(nt * cap, dtype=torch.float64, device=dev))
+        cnt = Counts()
+        self._check(lib().eph_rates_kbatch(self._h, C.byref(params), ns, _dptr(buffers["k"]), _dptr(buffers["n"]),
+                                           _dptr(buffers["e"]), _dptr(buffers["v"]), _dptr(buffers["it"]),
+                                           C.byref(cnt), int(q_batch)))
+        return RatesResult(buffers["k"][:ns], buffers["n"][:ns], buffers["e"][:ns], buffers["v"][:ns],
+                           buffers["it"][:nt * ns].view(nt, ns), cnt.as_dict()), buffers
+
     def bte_iterate(self, gamma, res, n_kpoints, max_iter=20, tol=1e-6, want_f=False, stream=None):
         """(sigma per iteration [n_done+1][nt][3][3], n_done, F or None)."""
         import torch
@@ -420,7 +443,7 @@ class _Bte:
 
 for _name in ("transport", "carrier_density"):
     setattr(Context, _name, getattr(_Transport, _name))
-for _name in ("gamma_estimate", "rates_gamma", "bte_iterate"):
+for _name in ("gamma_estimate", "rates_gamma", "bte_iterate", "rates_kbatch"):
     setattr(Context, _name, getattr(_Bte, _name))
 
 
@@ -456,7 +479,7 @@ class Mlp:
         import torch
         n = int(state_k.shape[0])
         dev = state_k.device
-        x = torch.empty((max(n, 1), 7), dtype=torch.float32, device=dev)
+        x = torch.empty((max(n, 1), MLP_FEATURES), dtype=torch.float32, device=dev)
         y = None
         nt = 0
         if inv_tau is not None:

@@ -156,3 +156,85 @@ def surrogate(workload_name="al_fcc_200", train_frac=0.02, chunks=8, threshold=0
          f"{r.n_flagged}/{r.n_states}, sigma rel err {err:.2e} (network only {err_net:.2e})")
     ctx.close()
     return out
+
+
+def _budget_parts(ctx, N, mu, w, lo, hi):
+    """(fixed bytes, bytes per state of a batch, states per group) of a rates
+    call, from the minimum that too small a mem_budget_bytes reports."""
+    import re
+    from .eph import EphError
+    msg = ""
+    for b in (1, None):
+        try:
+            bb = b if b is not None else int(re.search(r"\((\d+) bytes\)", msg).group(1)) + 1
+            ctx.count_states(ctx.params(N, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi))
+            ctx.scattering_rates(ctx.params(N, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi,
+                                            mem_budget_bytes=bb))
+        except EphError as e:
+            msg = str(e)
+    m = re.search(r"\((\d+) bytes of tables and lists plus (\d+) bytes per state of a batch, (\d+) states", msg)
+    return int(m.group(1)), int(m.group(2)), int(m.group(3))
+
+
+def ablation(workload_name="al_fcc_100", grid=40, q_batches=(16, 64, 256, 1024, 4096),
+             state_batches=(64, 256, 1024, 4096, 16384, None)):
+    """The comparison of Sec. III.D and the batch-size study of Sec. IV.C on
+    this GPU: the q-batch rate kernel against the k-batch order of the same
+    sum (eph_rates_kbatch) for several q-batch sizes, and the q-batch kernel
+    for several numbers of states per batch (mem_budget_bytes).  Per run:
+    time of the rates call and of its kernels, launches, (k,q) pairs per
+    second; the k-batch rates are checked against the q-batch ones."""
+    import torch
+    from synth import make_system, workload
+    from .eph import Context
+    w = workload(workload_name, grid)
+    s = make_system(w.system)
+    ctx = Context(s, device=0)
+    N = w.grid
+    mu, lo, hi = window(ctx, s, w, N)
+    out = {"report": "ablation", "workload": w.name, "grid": N, "q_batch": {}, "state_batch": {}}
+    p = ctx.params(N, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi)
+    _timed_rates(ctx, p)
+    ref, wall, st = _timed_rates(ctx, p)
+    n_kq = int(ref.counts["n_kq"])
+    it_ref = ref.inv_tau.cpu().numpy()
+    nw, nm = s.nw, 3 * s.na
+    nbox = s.rp.shape[0]
+    nre = s.re.shape[0]
+    out["n_states"] = int(ref.counts["n_states"])
+    out["n_kq"] = n_kq
+    out["n_nkq"] = int(ref.counts["n_nkq"])
+    # inner-product volume of the third step (complex MACs), Sec. III.D
+    out["volume_q_batch_cmac"] = float(ref.counts["n_nkq"]) * nw * nm * nbox
+    out["volume_k_batch_cmac"] = float(n_kq) * nw * nw * nre * nm
+    out["q_batch_order"] = {"call_s": wall, "rates_ms": st["rates_ms"], "xform_ms": st["xform_ms"],
+                            "launches": st["rates_launches"] + st["xform_launches"], "pairs_per_s": n_kq / wall}
+    _log(f"[ablation] {w.name} N={N}: {out['n_states']} states, {n_kq} (k,q) pairs; q-batch order {wall:.3f} s")
+    for qb in q_batches:
+        pk = ctx.params(N, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi)
+        ctx.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kb, _ = ctx.rates_kbatch(pk, q_batch=qb)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        stk = ctx.stage_times()
+        err = float(np.max(np.abs(kb.inv_tau.cpu().numpy() - it_ref)) / np.max(np.abs(it_ref)))
+        out["q_batch"][str(qb)] = {"call_s": t, "step1_ms": stk["xform_ms"], "step2_ms": stk["rates_ms"],
+                                   "launches": 2 * stk["rates_launches"], "pairs_per_s": n_kq / t,
+                                   "slowdown_vs_q_batch_order": t / wall, "inv_tau_rel_diff": err}
+        _log(f"[ablation] k-batch order, {qb} q per batch: {t:.3f} s ({t / wall:.1f}x), 1/tau diff {err:.1e}")
+    fixed, per_state, gmax = _budget_parts(ctx, N, mu, w, lo, hi)
+    for sb in state_batches:
+        budget = 0 if sb is None else fixed + per_state * max(sb, gmax)
+        pb = ctx.params(N, mu, w.temps, w.eta, lo, hi, w.band_lo, w.band_hi, mem_budget_bytes=budget)
+        _timed_rates(ctx, pb)
+        r2, t2, st2 = _timed_rates(ctx, pb)
+        same = bool(np.array_equal(r2.inv_tau.cpu().numpy(), it_ref))
+        key = "all" if sb is None else str(sb)
+        out["state_batch"][key] = {"call_s": t2, "rates_ms": st2["rates_ms"], "batches": st2["xform_launches"],
+                                   "launches": st2["rates_launches"] + st2["xform_launches"],
+                                   "pairs_per_s": n_kq / t2, "relative_time": t2 / wall, "bitwise_equal": same}
+        _log(f"[ablation] q-batch order, states per batch {key}: {t2:.3f} s in {st2['xform_launches']} batches")
+    ctx.close()
+    return out

@@ -32,4 +32,4 @@ def test_reference_forward_layer_shapes_and_silu():
     assert yhat.shape == (5, 2) and len(zs) == 3 and len(hs) == 4
     z = np.linspace(-5, 5, 11)
     assert np.allclose(ref.silu(z), z / (1 + np.exp(-z)))
-    assert ref.n_params(1) == 34177
+    assert ref.n_params(1) == 34561  # 10 inputs: 128*10 + 128 + 2*(128*128 + 128) + 128 + 1
