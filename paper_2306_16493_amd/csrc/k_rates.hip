@@ -21,29 +21,11 @@
 // energy-conserving (q, m) pairs rather than with all bands.
 // Accumulation of 1/tau is per thread in registers and reduced in a fixed
 // order at the end (no floating-point atomics).
+#include "dev_util.h"
 #include "internal.h"
 
 namespace eph {
 namespace {
-
-template <class T>
-struct V2;
-template <>
-struct V2<double> {
-  using t = double2;
-};
-template <>
-struct V2<float> {
-  using t = float2;
-};
-
-template <class T>
-__device__ __forceinline__ typename V2<T>::t mk(T x, T y) {
-  typename V2<T>::t r;
-  r.x = x;
-  r.y = y;
-  return r;
-}
 
 __device__ __forceinline__ int pmod(int64_t a, int N) {
   int64_t r = a % N;
@@ -72,8 +54,6 @@ __device__ __forceinline__ int upper_bound_lds(const double *a, int n, double x)
 struct Smem {
   size_t tab, y, z, le, lk, mask, misc, total;
 };
-
-__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 template <class T>
 __host__ __device__ inline Smem smem_layout(int N, int nw, int C, int smax, RpBox box) {
