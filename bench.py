@@ -33,23 +33,36 @@ METRIC = "(k,q) el-ph pair evals/s + σ wall time at ≤1e-3 rel σ error vs FP6
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 157.3}
 
 
+# sources that define the rate-kernel instances (template, dispatch, instances)
+KERNEL_SOURCES = ("rates_wave.h", "k_rates_wave.hip", "k_rates_wave_d3.hip", "k_rates_wave_s3.hip",
+                  "k_rates_wave_d6.hip", "k_rates_wave_s6.hip", "dev_util.h", "internal.h")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2306_16493_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, precision):
     """HBM bytes per rate-kernel launch from the committed counter summary
     (profiles/rates_wave_traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch,
-    scaled by a copy kernel of known size), or None when that summary was
-    taken on another workload or on a different kernel source."""
-    import hashlib
+    scaled by a copy kernel of known size), or None when no entry was taken
+    on this workload and form with the present kernel sources."""
     path = os.path.join(ROOT, "profiles", "rates_wave_traffic.json")
-    src = os.path.join(ROOT, "paper_2306_16493_amd", "csrc", "k_rates_wave.hip")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        t = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if t.get("source_sha256") != sha or t.get("workload") != workload or t.get("precision") != precision:
-        return None
-    return t["fetch_kib_per_launch"] * 1024 * t["fetch_scale"] + t["write_kib_per_launch"] * 1024 * t["write_scale"]
+        entries = json.load(f).get("entries", [])
+    sha = kernel_source_sha()
+    for t in entries:
+        if t.get("source_sha256") == sha and t.get("workload") == workload and t.get("precision") == precision:
+            return (t["fetch_kib_per_launch"] * 1024 * t["fetch_scale"] +
+                    t["write_kib_per_launch"] * 1024 * t["write_scale"])
+    return None
 
 
 def rate_kernel_flops(counts, ns, N, box, C, nm, nw):
@@ -136,6 +149,10 @@ def main():
                     help="instead of the bench line, measure the FP32/BF16x3 forms or the surrogate on "
                          "their own workloads (one JSON line)")
     ap.add_argument("--subset-frac", type=float, default=0.01, help="k-point fraction of --report precision")
+    ap.add_argument("--only", choices=["fp64", "fp32", "bf16x3"], default=None,
+                    help="time only this form for --steps after --warmup (no other forms, no oracle baseline) and "
+                         "print its kernel times; for profiler runs")
+    ap.add_argument("--source-sha", action="store_true", help="print the hash of the rate-kernel sources")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -143,6 +160,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
 
+    if args.source_sha:
+        print(kernel_source_sha())
+        return
     import numpy as np
     import torch
     if args.copy_calibration:
@@ -211,6 +231,15 @@ def main():
         return dict(t=t, step_s=step_s, res=res, sig=sig, rates_ms=float(np.mean(rates_ms)),
                     xform_ms=float(np.mean(xform_ms)), launches=launches / steps, st=st)
 
+    if args.only:
+        one = timed(args.only, args.warmup, args.steps)
+        print(json.dumps({"only": args.only, "workload": w.name, "grid": w.grid, "steps": args.steps,
+                          "ms_per_step": one["t"] * 1e3, "rates_ms": one["rates_ms"], "xform_ms": one["xform_ms"],
+                          "rate_launches_per_step": one["launches"],
+                          "avg_rate_launch_ms": one["rates_ms"] / one["launches"],
+                          "n_kq": one["res"].counts["n_kq"]}), flush=True)
+        ctx.close()
+        return
     # the FP64 path (the reference of the sigma error), then the reduced
     # forms; the headline is the fastest form within 1e-3 relative sigma
     # error of the FP64 run, timed for the requested steps
