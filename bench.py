@@ -145,10 +145,15 @@ def main():
                     help="form of the headline: auto (the fastest within 1e-3 relative sigma error of the FP64 "
                          "run), fp64, fp32 or bf16x3")
     ap.add_argument("--cpu-sample", type=int, default=40, help="k points of the oracle sample (0 = skip)")
-    ap.add_argument("--report", choices=["precision", "surrogate", "ablation"], default=None,
+    ap.add_argument("--report", choices=["precision", "surrogate", "surrogate-sweep", "ablation"], default=None,
                     help="instead of the bench line, measure the FP32/BF16x3 forms or the surrogate on "
                          "their own workloads (one JSON line)")
     ap.add_argument("--subset-frac", type=float, default=0.01, help="k-point fraction of --report precision")
+    ap.add_argument("--train-fracs", default="0.02,0.05", help="training fractions of --report surrogate-sweep")
+    ap.add_argument("--thresholds", default="0.01,0.02,0.05", help="spread thresholds of --report surrogate-sweep")
+    ap.add_argument("--reference", default=None,
+                    help="JSON with the sigma and time of the full plain run (--report surrogate-sweep; measured "
+                         "when absent)")
     ap.add_argument("--only", choices=["fp64", "fp32", "bf16x3"], default=None,
                     help="time only this form for --steps after --warmup (no other forms, no oracle baseline) and "
                          "print its kernel times; for profiler runs")
@@ -177,6 +182,18 @@ def main():
         from paper_2306_16493_amd import reports
         wl = args.workload or "si_fcc_150"
         print(json.dumps(reports.precision(wl, args.subset_frac, grid=args.grid)), flush=True)
+        return
+    if args.report == "surrogate-sweep":
+        from paper_2306_16493_amd import reports
+        ref = None
+        if args.reference:
+            with open(args.reference) as f:
+                ref = json.load(f)
+        fr = [float(x) for x in args.train_fracs.split(",") if x]
+        th = [float(x) for x in args.thresholds.split(",") if x]
+        prec = args.precision if args.precision != "auto" else "fp32"
+        print(json.dumps(reports.surrogate_sweep(args.workload or "al_fcc_200", fr, th, grid=args.grid,
+                                                 precision=prec, ref=ref)), flush=True)
         return
     if args.report == "ablation":
         from paper_2306_16493_amd import reports

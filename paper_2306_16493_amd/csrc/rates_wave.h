@@ -215,7 +215,9 @@ void rates_wave_kernel(RatesArgs a) {
   }
 
   // One candidate = (k-slot, p1, Z slot): every state of that k point against
-  // every final band m at p = k + q.
+  // every final band m at p = k + q.  Queue item (32 bits): p1 | ks << 10 |
+  // zslot << 15 | (mask of the bands inside the prefilter window) << 17.
+  static_assert(NZ <= 4 && NW <= 8 && SMX <= 32, "candidate item fields");
   int qn = 0;
   // Two-level form: stage1(n) sieves the first n queued candidates against
   // every (state, final band) pair and appends the pairs with a kept term to
@@ -429,7 +431,8 @@ void rates_wave_kernel(RatesArgs a) {
       const int i = base + lane;
       const bool act = i < count;
       const uint32_t it = act ? sQ[i] : 0u;
-      const int p1 = (int)(it & 1023u), ks = (int)((it >> 10) & 31u), zs_slot = (int)(it >> 15);
+      const int p1 = (int)(it & 1023u), ks = (int)((it >> 10) & 31u), zs_slot = (int)((it >> 15) & 3u);
+      const unsigned bmask = it >> 17;  // final bands that passed the prefilter (0 for idle lanes)
       const int line = sSlot[2 * zs_slot + 1], q2 = sSlot[2 * zs_slot];
       int q1 = p1 - sK1[ks];
       q1 += (q1 < 0) ? N : 0;
@@ -441,6 +444,15 @@ void rates_wave_kernel(RatesArgs a) {
       for (int nu = 0; nu < NM; nu++) om[nu] = act ? a.om[qidx * NM + nu] : 0.0;
 #pragma unroll
       for (int m = 0; m < NW; m++) ep[m] = act ? a.eps[pidx * NW + m] : 0.0;
+      // modes above the frequency cut (branch-free bit mask)
+      unsigned okw = 0u;
+#pragma unroll
+      for (int nu = 0; nu < NM; nu++) okw |= (om[nu] >= a.wcut) ? (1u << nu) : 0u;
+      // bands some lane needs: a band outside the prefilter window of every
+      // lane's k-slot keeps no term, so it is skipped by the whole wave
+      unsigned long long band_any[NW];
+#pragma unroll
+      for (int m = 0; m < NW; m++) band_any[m] = __ballot((bmask >> m) & 1u);
       const int sf = sKfirst[ks], sc = act ? sKcnt[ks] : 0;
       double esr[NW];
 #pragma unroll
@@ -451,18 +463,28 @@ void rates_wave_kernel(RatesArgs a) {
         if (j >= KMX) break;  // wave-uniform
         const int s = sf + j;
         const bool sv = j < sc;
+        const unsigned okj = sv ? okw : 0u;
         const double es = esr[j];
+        // (es + w) and (es - w) once per state, in the oracle's order
+        double wp[NM], wm[NM];
+#pragma unroll
+        for (int nu = 0; nu < NM; nu++) {
+          wp[nu] = es + om[nu];
+          wm[nu] = es - om[nu];
+        }
         bool hit_s = false;
         unsigned nterm = 0;
 #pragma unroll
         for (int m = 0; m < NW; m++) {
-          unsigned vp = 0, vm = 0;
+          if (!band_any[m]) continue;  // wave-uniform
+          unsigned vp = 0u, vm = 0u;
 #pragma unroll
           for (int nu = 0; nu < NM; nu++) {
-            const bool okw = sv && om[nu] >= a.wcut;
-            vp |= (okw && fabs(es + om[nu] - ep[m]) <= cut) ? (1u << nu) : 0u;
-            vm |= (okw && fabs(es - om[nu] - ep[m]) <= cut) ? (1u << nu) : 0u;
+            vp |= (fabs(wp[nu] - ep[m]) <= cut) ? (1u << nu) : 0u;
+            vm |= (fabs(wm[nu] - ep[m]) <= cut) ? (1u << nu) : 0u;
           }
+          vp &= okj;
+          vm &= okj;
           const bool any = (vp | vm) != 0u;
           hit_s |= any;
           nterm += (unsigned)(__popc(vp) + __popc(vm));
@@ -544,7 +566,7 @@ void rates_wave_kernel(RatesArgs a) {
       {  // the Z slot is reused: evaluate queued work that still points at it
         bool stale = false;
         for (int b = 0; b < qn; b += 64)
-          stale |= (b + lane < qn) && (int)(sQ[b + lane] >> 15) == zslot;
+          stale |= (b + lane < qn) && (int)((sQ[b + lane] >> 15) & 3u) == zslot;
         for (int b = 0; b < vn; b += 64)
           stale |= (b + lane < vn) && (int)(sV[b + lane].x >> 30) == zslot;
         if (__any(stale)) {
@@ -612,17 +634,18 @@ void rates_wave_kernel(RatesArgs a) {
         const float lo_w = (float)(sEps[sf] - W), hi_w = (float)(sEps[sf + sc - 1] + W);
         for (int c0 = 0; c0 < N; c0 += 64) {
           const int p1 = c0 + lane;
-          bool any = false;
+          unsigned bm = 0u;  // bands of this p1 inside the window
           if (p1 < N) {
 #pragma unroll
             for (int m = 0; m < NW; m++) {
               const float ev = sLine[m * N + p1];
-              any |= (ev >= lo_w) & (ev <= hi_w);
+              bm |= ((ev >= lo_w) & (ev <= hi_w)) ? (1u << m) : 0u;
             }
           }
+          const bool any = bm != 0u;
           const unsigned long long bits = __ballot(any);
           if (any) sQ[qn + __popcll(bits & ((1ull << lane) - 1ull))] =
-              (uint32_t)p1 | ((uint32_t)ks << 10) | ((uint32_t)zslot << 15);
+              (uint32_t)p1 | ((uint32_t)ks << 10) | ((uint32_t)zslot << 15) | (bm << 17);
           qn += __popcll(bits);
           __syncwarp();
           if (qn >= 64) {  // whole passes only, so the queue stays below 128

@@ -158,6 +158,75 @@ def surrogate(workload_name="al_fcc_200", train_frac=0.02, chunks=8, threshold=0
     return out
 
 
+def surrogate_sweep(workload_name="al_fcc_200", train_fracs=(0.02, 0.05), thresholds=(0.01, 0.02, 0.05),
+                    members=5, steps=3000, seed=1649307, grid=None, precision="fp32", ref=None, chunks=8):
+    """The surrogate over training fractions and spread thresholds against
+    one full plain run.  The plain run (unless `ref` gives its sigma and
+    time) is timed over disjoint k-point chunks; the table time every chunk
+    call repeats is taken off all but one.  Per training fraction the
+    ensemble is fitted once; per threshold the blend, the plain fallback and
+    sigma are timed on their own, so each setting's time is selection +
+    training rates + fit + prediction + blend + fallback."""
+    import torch
+    from synth import make_system, workload
+    from .eph import Context, merge_rates
+    from . import surrogate as sg
+    w = workload(workload_name, grid)
+    s = make_system(w.system)
+    ctx = Context(s, device=0)
+    N = w.grid
+    mu, lo, hi = window(ctx, s, w, N)
+    temps = list(w.temps)
+    P = lambda ks: ctx.params(N, mu, temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision=precision, k_subset=ks)
+    out = {"report": "surrogate_sweep", "workload": w.name, "grid": N, "precision": precision, "members": members,
+           "train_steps": steps, "settings": []}
+    if ref is None:
+        ctx.set_profiling(True)
+        sk, sn, se, sv = ctx.select_states(P(None))
+        kall = np.unique(sk.cpu().numpy())
+        inv = torch.zeros((len(temps), sk.shape[0]), dtype=torch.float64, device=sk.device)
+        t_sum, t_tab = 0.0, []
+        parts = [x for x in np.array_split(kall, chunks) if x.size]
+        for i, ks in enumerate(parts):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, _ = ctx.scattering_rates(P(ks))
+            torch.cuda.synchronize()
+            t_sum += time.perf_counter() - t0
+            t_tab.append(ctx.stage_times()["tables_ms"] / 1e3)
+            merge_rates(ctx, sk, sn, inv, res.state_k, res.state_n, res.inv_tau)
+            _log(f"[sweep] plain chunk {i + 1}/{len(parts)}: {res.counts['n_states']} states, {t_sum:.1f} s")
+        sig_ref = ctx.conductivity(se, sv, inv.reshape(-1), mu, temps, N ** 3)
+        ref = {"sigma": sig_ref.tolist(), "plain_s": t_sum - sum(t_tab[1:]), "plain_chunks_s": t_sum,
+               "tables_s_per_call": float(np.mean(t_tab)), "n_states": int(sk.shape[0]), "k_points": int(kall.size)}
+        del inv
+        _log(f"[sweep] plain run {ref['plain_s']:.1f} s ({t_sum:.1f} s over {len(parts)} chunk calls)")
+    out["reference"] = ref
+    sig_ref = np.asarray(ref["sigma"])
+    scale = np.max(np.abs(sig_ref))
+    for tf in train_fracs:
+        f = sg.fit(ctx, N, mu, temps, w.eta, lo, hi, w.band_lo, w.band_hi, train_frac=tf, members=members,
+                   steps=steps, seed=seed, precision=precision, log=_log)
+        for th in thresholds:
+            r = sg.finish(f, th, log=_log)
+            sk, sn, se, sv = r.states
+            err = float(np.max(np.abs(r.sigma - sig_ref)) / scale)
+            sig_net = ctx.conductivity(se, sv, r.raw_inv_tau.reshape(-1), mu, temps, N ** 3)
+            err_net = float(np.max(np.abs(sig_net - sig_ref)) / scale)
+            t = r.times["total_s"]
+            row = {"train_frac": tf, "threshold": th, "n_states": int(r.n_states), "train_k_points": int(r.n_train_k),
+                   "flagged_states": int(r.n_flagged), "flagged_frac": r.n_flagged / r.n_states,
+                   "fallback_k_points": int(r.n_fallback_k), "sigma_rel_err": err,
+                   "sigma_rel_err_network_only": err_net, "surrogate_s": t, "speedup": ref["plain_s"] / t,
+                   "member_loss": [float(x) for x in r.loss], "stage_s": r.times}
+            out["settings"].append(row)
+            _log(f"[sweep] train {tf:.0%} threshold {th:.0%}: flagged {row['flagged_frac']:.1%}, sigma err {err:.2e} "
+                 f"(network only {err_net:.2e}), {t:.1f} s, speedup {row['speedup']:.2f}x")
+        f.mlp.close()
+    ctx.close()
+    return out
+
+
 def _budget_parts(ctx, N, mu, w, lo, hi):
     """(fixed bytes, bytes per state of a batch, states per group) of a rates
     call, from the minimum that too small a mem_budget_bytes reports."""

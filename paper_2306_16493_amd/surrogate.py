@@ -40,11 +40,28 @@ class SurrogateResult:
     fallback_k: "object" = None  # k points recomputed by the plain kernel
 
 
-def run(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_frac=0.02, members=5,
-        steps=2000, batch=256, lr=2e-3, threshold=0.01, seed=1649307, precision="fp64", log=None,
-        fallback_chunk=400000):
+@dataclass
+class Fitted:
+    """Steps 1-4 done: the window states, the training rates, the ensemble's
+    prediction; finish() takes it through steps 5-6 for one threshold."""
+    ctx: "object"
+    P: "object"
+    temps: list
+    grid: int
+    mu: float
+    states: tuple
+    train: "object"            # plain result at the training k points
+    ktrain: np.ndarray
+    y: "object"                # ensemble predictions (members x states x temps)
+    mlp: "object"
+    loss: np.ndarray
+    times: dict
+
+
+def fit(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_frac=0.02, members=5,
+        steps=2000, batch=256, lr=2e-3, seed=1649307, precision="fp64", log=None):
     import torch
-    from .eph import Mlp, merge_rates
+    from .eph import Mlp
 
     def say(*a):
         if log:
@@ -78,31 +95,61 @@ def run(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_
     torch.cuda.synchronize()
     times["fit_s"] = time.perf_counter() - t2
     say(f"[surrogate] member losses {np.array2string(loss, precision=4)}")
-    # ---- predict everything, flag disagreement ----
+    # ---- predict every state ----
     t3 = time.perf_counter()
     x_all, _ = mlp.features(sk, se, sv, grid, mu)
     y = mlp.predict(x_all)
-    inv_tau, flag, nflag = mlp.blend(y, threshold)
-    raw = inv_tau.clone()
     torch.cuda.synchronize()
     times["predict_s"] = time.perf_counter() - t3
+    return Fitted(ctx, P, temps, grid, mu, (sk, sn, se, sv), tr, ktrain, y, mlp, loss, times)
+
+
+def finish(f, threshold=0.01, log=None, fallback_chunk=400000):
+    import torch
+    from .eph import merge_rates
+
+    def say(*a):
+        if log:
+            log(*a)
+
+    ctx = f.ctx
+    sk, sn, se, sv = f.states
+    times = dict(f.times)
+    t3 = time.perf_counter()
+    inv_tau, flag, nflag = f.mlp.blend(f.y, threshold)
+    raw = inv_tau.clone()
+    torch.cuda.synchronize()
+    times["blend_s"] = time.perf_counter() - t3
     # ---- fallback: plain rates at the k points of flagged states ----
     t4 = time.perf_counter()
+    tr = f.train
     merge_rates(ctx, sk, sn, inv_tau, tr.state_k, tr.state_n, tr.inv_tau)
     kflag = np.unique(sk[flag.bool()].cpu().numpy()) if nflag else np.zeros(0, np.int64)
-    kflag = np.setdiff1d(kflag, ktrain)
+    kflag = np.setdiff1d(kflag, f.ktrain)
     # in chunks of at most fallback_chunk k points (bounded buffers, progress)
     for c0 in range(0, kflag.size, fallback_chunk):
-        fb, _ = ctx.scattering_rates(P(kflag[c0:c0 + fallback_chunk]))
+        fb, _ = ctx.scattering_rates(f.P(kflag[c0:c0 + fallback_chunk]))
         merge_rates(ctx, sk, sn, inv_tau, fb.state_k, fb.state_n, fb.inv_tau)
         torch.cuda.synchronize()
         say(f"[surrogate] fallback {min(c0 + fallback_chunk, kflag.size)}/{kflag.size} k points, "
             f"{time.perf_counter() - t4:.1f} s")
     torch.cuda.synchronize()
     times["fallback_s"] = time.perf_counter() - t4
-    say(f"[surrogate] {nflag} states flagged, plain fallback at {kflag.size} k points")
-    sig = ctx.conductivity(se, sv, inv_tau.reshape(-1), mu, temps, grid ** 3)
-    times["total_s"] = time.perf_counter() - t0
-    mlp.close()
-    return SurrogateResult(inv_tau, sig, ns, ntk, int(tr.state_k.shape[0]), nflag, int(kflag.size), loss, times,
-                           (sk, sn, se, sv), raw, ktrain, kflag)
+    say(f"[surrogate] threshold {threshold}: {nflag} states flagged, plain fallback at {kflag.size} k points")
+    sig = ctx.conductivity(se, sv, inv_tau.reshape(-1), f.mu, f.temps, f.grid ** 3)
+    times["total_s"] = sum(times[k] for k in ("select_s", "train_rates_s", "fit_s", "predict_s", "blend_s",
+                                              "fallback_s"))
+    return SurrogateResult(inv_tau, sig, int(sk.shape[0]), int(f.ktrain.size), int(tr.state_k.shape[0]), nflag,
+                           int(kflag.size), f.loss, times, f.states, raw, f.ktrain, kflag)
+
+
+def run(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_frac=0.02, members=5,
+        steps=2000, batch=256, lr=2e-3, threshold=0.01, seed=1649307, precision="fp64", log=None,
+        fallback_chunk=400000):
+    """Steps 1-6 for one threshold."""
+    f = fit(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo, band_hi, train_frac, members, steps, batch, lr,
+            seed, precision, log)
+    try:
+        return finish(f, threshold, log, fallback_chunk)
+    finally:
+        f.mlp.close()
