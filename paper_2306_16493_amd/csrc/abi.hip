@@ -24,6 +24,32 @@ Units units() {
   return u;
 }
 
+// Electron tables (eps, V, v on the N^3 grid): the separable Bloch sum
+// when the H(R) list has a dense box, else the direct sum over the list.
+hipError_t electron_tables(eph_ctx *c, int N, const Units &U, hipStream_t st) {
+  const int64_t NQ = (int64_t)N * N * N;
+  if (c->hbox_n[0] > 0)
+    return launch_bloch_lines(0, c->nw, N, c->hbox_lo, c->hbox_n, c->lattice, c->hbox.as<double2>(),
+                              c->tab.as<double2>(), nullptr, U.cph_ev, 0.0, U.vel_unit, c->eps.as<double>(),
+                              c->evec.as<double2>(), c->vel.as<double>(), nullptr, st);
+  return launch_bloch_eig(0, c->nw, N, 0, NQ, c->nrh, c->rh.as<int>(), c->rh_w.as<double>(), c->rh_cart.as<double>(),
+                          c->ham.as<double2>(), c->tab.as<double2>(), nullptr, U.cph_ev, 0.0, U.vel_unit,
+                          c->eps.as<double>(), c->evec.as<double2>(), c->vel.as<double>(), nullptr, st);
+}
+
+// Phonon tables (hbar w, u on the N^3 grid), the same two forms.
+hipError_t phonon_tables(eph_ctx *c, int N, const Units &U, double omega_cut, unsigned long long *n_excluded,
+                         hipStream_t st) {
+  const int64_t NQ = (int64_t)N * N * N;
+  if (c->dbox_n[0] > 0)
+    return launch_bloch_lines(1, c->nm, N, c->dbox_lo, c->dbox_n, c->lattice, c->dbox.as<double2>(),
+                              c->tab.as<double2>(), c->mode_mass_d.as<double>(), U.cph_ev, omega_cut, U.vel_unit,
+                              c->om.as<double>(), c->uu.as<double2>(), nullptr, n_excluded, st);
+  return launch_bloch_eig(1, c->nm, N, 0, NQ, c->nrd, c->rd.as<int>(), c->rd_w.as<double>(), nullptr,
+                          c->dyn.as<double2>(), c->tab.as<double2>(), c->mode_mass_d.as<double>(), U.cph_ev,
+                          omega_cut, U.vel_unit, c->om.as<double>(), c->uu.as<double2>(), nullptr, n_excluded, st);
+}
+
 DevBuf::~DevBuf() {
   if (p) (void)hipFree(p);
 }
@@ -306,7 +332,39 @@ int32_t eph_load_wannier(const eph_model *m, int32_t device, eph_ctx **out) {
             wt[2 * dst] = m->gw[2 * src];
             wt[2 * dst + 1] = m->gw[2 * src + 1];
           }
+  // dense weighted boxes for the separable Bloch sum, when the R list fills
+  // at least a quarter of its bounding box and the box is short along R1
+  auto dense_box = [&](int nr, const int *R, const double *w, const double *M, int n, int *lo, int *nb,
+                       std::vector<double> &box) {
+    int hi[3];
+    for (int a = 0; a < 3; a++) lo[a] = hi[a] = R[a];
+    for (int r = 0; r < nr; r++)
+      for (int a = 0; a < 3; a++) {
+        lo[a] = std::min(lo[a], R[3 * r + a]);
+        hi[a] = std::max(hi[a], R[3 * r + a]);
+      }
+    for (int a = 0; a < 3; a++) nb[a] = hi[a] - lo[a] + 1;
+    const int64_t cells = (int64_t)nb[0] * nb[1] * nb[2];
+    if (nb[0] > kBoxMaxR1 || cells > 4 * (int64_t)nr) {
+      nb[0] = nb[1] = nb[2] = 0;
+      return;
+    }
+    const size_t nn = (size_t)n * n;
+    box.assign(2 * (size_t)cells * nn, 0.0);
+    for (int r = 0; r < nr; r++) {
+      const size_t cell = ((size_t)(R[3 * r] - lo[0]) * nb[1] + (R[3 * r + 1] - lo[1])) * nb[2] + (R[3 * r + 2] - lo[2]);
+      for (size_t x = 0; x < 2 * nn; x++) box[2 * cell * nn + x] += w[r] * M[2 * (size_t)r * nn + x];
+    }
+  };
+  std::vector<double> hb, db;
+  dense_box(m->n_rh, m->rh, m->rh_w, m->ham, nw, c->hbox_lo, c->hbox_n, hb);
+  dense_box(m->n_rd, m->rd, m->rd_w, dyn.data(), nm, c->dbox_lo, c->dbox_n, db);
   hipError_t e;
+  if ((!hb.empty() && (e = upload(c->hbox, hb.data(), hb.size())) != hipSuccess) ||
+      (!db.empty() && (e = upload(c->dbox, db.data(), db.size())) != hipSuccess)) {
+    (void)hipGetLastError();
+    return bad(e == hipErrorOutOfMemory ? EPH_E_NOMEM : EPH_E_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+  }
   if ((e = upload(c->rh, m->rh, 3 * (size_t)m->n_rh)) != hipSuccess ||
       (e = upload(c->rh_w, m->rh_w, (size_t)m->n_rh)) != hipSuccess ||
       (e = upload(c->rh_cart, cart.data(), cart.size())) != hipSuccess ||
@@ -411,13 +469,8 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
   //      6 vertex contractions
   EPH_HIP(c, launch_zero(ctr, sizeof(unsigned long long) * 8, st));
   EPH_HIP(c, launch_phase_table(N, c->tab.as<double2>(), st));
-  EPH_HIP(c, launch_bloch_eig(0, nw, N, 0, NQ, c->nrh, c->rh.as<int>(), c->rh_w.as<double>(), c->rh_cart.as<double>(),
-                              c->ham.as<double2>(), c->tab.as<double2>(), nullptr, U.cph_ev, 0.0, U.vel_unit,
-                              c->eps.as<double>(), c->evec.as<double2>(), c->vel.as<double>(), nullptr, st));
-  EPH_HIP(c, launch_bloch_eig(1, nm, N, 0, NQ, c->nrd, c->rd.as<int>(), c->rd_w.as<double>(), nullptr,
-                              c->dyn.as<double2>(), c->tab.as<double2>(), c->mode_mass_d.as<double>(), U.cph_ev,
-                              p->omega_cut_eV, U.vel_unit, c->om.as<double>(), c->uu.as<double2>(), nullptr, ctr + 0,
-                              st));
+  EPH_HIP(c, electron_tables(c, N, U, st));
+  EPH_HIP(c, phonon_tables(c, N, U, p->omega_cut_eV, ctr + 0, st));
   const bool fp32 = p->precision != EPH_FP64;
   if (fp32) {  // FP32 copies of the rotation tables for the reduced-precision forms
     EPH_HIP(c, c->evec32.ensure(sizeof(float2) * NQ * nw * nw));
@@ -1173,9 +1226,7 @@ int32_t eph_carrier_density(eph_ctx *c, int32_t grid, int32_t band_lo, int32_t b
   EPH_HIP(c, c->evec.ensure(sizeof(double2) * NQ * nw * nw));
   EPH_HIP(c, c->vel.ensure(sizeof(double) * NQ * nw * 3));
   EPH_HIP(c, launch_phase_table(N, c->tab.as<double2>(), st));
-  EPH_HIP(c, launch_bloch_eig(0, nw, N, 0, NQ, c->nrh, c->rh.as<int>(), c->rh_w.as<double>(), c->rh_cart.as<double>(),
-                              c->ham.as<double2>(), c->tab.as<double2>(), nullptr, U.cph_ev, 0.0, U.vel_unit,
-                              c->eps.as<double>(), c->evec.as<double2>(), c->vel.as<double>(), nullptr, st));
+  EPH_HIP(c, electron_tables(c, N, U, st));
   const int nblk = 256;
   EPH_HIP(c, c->sig_part.ensure(sizeof(double) * ((size_t)nblk * EPH_MAX_TEMPS + 2 * EPH_MAX_TEMPS)));
   double *part = c->sig_part.as<double>();

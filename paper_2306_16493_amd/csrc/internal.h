@@ -74,6 +74,10 @@ struct eph_ctx {
   // device copies of the model
   eph::DevBuf rh, rh_w, rh_cart, ham;   // ham: [nrh][nw*nw] double2
   eph::DevBuf rd, rd_w, dyn;            // dyn: Phi/sqrt(MM') as double2 [nrd][nm*nm]
+  // dense boxes of the weighted H(R) and D(R) for the separable Bloch sum
+  // (empty when the R list does not fill its box well enough)
+  eph::DevBuf hbox, dbox;
+  int hbox_lo[3] = {0, 0, 0}, hbox_n[3] = {0, 0, 0}, dbox_lo[3] = {0, 0, 0}, dbox_n[3] = {0, 0, 0};
   eph::DevBuf re;                       // [nre][3] int
   eph::DevBuf wt64;                     // [nre*nw][box*nm*nw] double2 (K-major)
   eph::DevBuf wt32;                     // same in float2 (lazy)
@@ -145,6 +149,15 @@ hipError_t launch_bloch_eig(int mode, int n, int N, int64_t k0, int64_t nk, int 
                             double *eval, double2 *evec, double *vel, unsigned long long *n_excluded,
                             hipStream_t st);
 hipError_t launch_phase_table(int N, double2 *tab, hipStream_t st);
+// The same tables for all N^3 grid points from the separable form of the
+// Bloch sum: Mb is the dense copy [nb0][nb1][nb2][n][n] of the weighted
+// matrices on the box [lo, lo + nb) of R vectors (zero where the list has
+// no vector), nb[0] <= kBoxMaxR1; lattice as rows a1, a2, a3 (Angstrom).
+constexpr int kBoxMaxR1 = 12;
+hipError_t launch_bloch_lines(int mode, int n, int N, const int *lo, const int *nb, const double *lattice,
+                              const double2 *Mb, const double2 *tab, const double *mode_mass, double cph,
+                              double omega_cut, double vel_unit, double *eval, double2 *evec, double *vel,
+                              unsigned long long *n_excluded, hipStream_t st);
 
 // State selection.  cnt/offs sized nklist+1.
 hipError_t launch_count_states(int64_t nklist, const int64_t *klist, int nw, const double *eps, int blo,

@@ -15,6 +15,7 @@
 // NP/2 disjoint complex rotations at once, each lane updating its element of
 // A and V from the (at most four) elements of the two rows/columns it mixes,
 // staged in LDS.  Everything stays in FP64.
+#include "dev_util.h"
 #include "internal.h"
 
 namespace eph {
@@ -45,60 +46,31 @@ struct Rot {
   double2 se;  // s e^{i phi}
 };
 
-template <int NP>
-__global__ __launch_bounds__(64) void bloch_eig_kernel(int mode, int n, int N, int64_t k0, int64_t nk, int nr,
-                                                       const int *__restrict__ R, const double *__restrict__ w,
-                                                       const double *__restrict__ Rcart,
-                                                       const double2 *__restrict__ M,
-                                                       const double2 *__restrict__ tab,
-                                                       const double *__restrict__ mode_mass, double cph,
-                                                       double omega_cut, double vel_unit, double *__restrict__ eval,
-                                                       double2 *__restrict__ evec, double *__restrict__ vel,
-                                                       unsigned long long *__restrict__ n_excluded) {
-  constexpr int L = NP * NP;
-  constexpr int MPW = 64 / L;
-  __shared__ double2 sA[64];
-  __shared__ double2 sV[64];
-  __shared__ Rot sR[64];
-  __shared__ double sW[64];
+// Outputs of the eigensolve, shared by both Bloch-sum forms.
+struct EigOut {
+  int mode, n;
+  const double *mode_mass;
+  double cph, omega_cut, vel_unit;
+  double *eval;
+  double2 *evec;
+  double *vel;
+  unsigned long long *n_excluded;
+};
 
+// Parallel cyclic Jacobi on the matrices of one wave (element (i, j) of
+// matrix mloc in each lane, acc its value, d0..d2 its k-derivatives), then
+// eigenvalues sorted ascending, eigenvectors (or mode amplitudes) and
+// velocities written for grid point kl.  The wave is the whole workgroup.
+template <int NP>
+__device__ __forceinline__ void eig_store(const EigOut &o, bool live, int64_t kl, double2 acc, double2 d0,
+                                          double2 d1, double2 d2, double2 *sA, double2 *sV, Rot *sR, double *sW) {
+  constexpr int L = NP * NP;
+  const int mode = o.mode, n = o.n;
   const int lane = threadIdx.x;
-  const int mloc = lane / L;
   const int e = lane % L;
   const int i = e / NP, j = e % NP;
   const bool valid_ij = (i < n) && (j < n);
-  const int base = mloc * L;
-
-  const int64_t ngroups = (nk + MPW - 1) / MPW;
-  for (int64_t gidx = blockIdx.x; gidx < ngroups; gidx += gridDim.x) {
-    const int64_t kl = gidx * MPW + mloc;
-    const bool live = kl < nk;
-    const int64_t kg = k0 + (live ? kl : 0);
-    const int64_t k1 = kg % N, k2 = (kg / N) % N, k3 = kg / ((int64_t)N * N);
-
-    // ---- Bloch sum (and derivatives for electrons) ----
-    double2 acc = make_double2(0.0, 0.0);
-    double2 d0 = acc, d1 = acc, d2 = acc;
-    if (valid_ij) {
-      for (int r = 0; r < nr; r++) {
-        int64_t s = (k1 * R[3 * r] + k2 * R[3 * r + 1] + k3 * R[3 * r + 2]) % N;
-        if (s < 0) s += N;
-        double2 ph = tab[s];
-        double wr = w[r];
-        ph.x *= wr;
-        ph.y *= wr;
-        double2 t = cmul(ph, M[(size_t)r * n * n + i * n + j]);
-        acc = cadd(acc, t);
-        if (mode == 0) {
-          // i * R_a * t
-          double2 it = make_double2(-t.y, t.x);
-          double r0 = Rcart[3 * r], r1 = Rcart[3 * r + 1], r2 = Rcart[3 * r + 2];
-          d0.x += r0 * it.x; d0.y += r0 * it.y;
-          d1.x += r1 * it.x; d1.y += r1 * it.y;
-          d2.x += r2 * it.x; d2.y += r2 * it.y;
-        }
-      }
-    }
+  const int base = (lane / L) * L;
     sA[lane] = valid_ij ? acc : make_double2(0.0, 0.0);
     sV[lane] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     __syncthreads();
@@ -193,20 +165,20 @@ __global__ __launch_bounds__(64) void bloch_eig_kernel(int mode, int n, int N, i
       const int64_t kk = kl;
       double2 v = sV[base + i * NP + j];
       if (mode == 0) {
-        if (i == 0) eval[kk * n + rank] = wj;
-        evec[(kk * n + rank) * n + i] = v;
+        if (i == 0) o.eval[kk * n + rank] = wj;
+        o.evec[(kk * n + rank) * n + i] = v;
       } else {
-        double hw = sqrt(cph * fmax(wj, 0.0));
+        double hw = sqrt(o.cph * fmax(wj, 0.0));
         if (i == 0) {
-          eval[kk * n + rank] = hw;
-          if (hw < omega_cut) atomicAdd(n_excluded, 1ull);
+          o.eval[kk * n + rank] = hw;
+          if (hw < o.omega_cut) atomicAdd(o.n_excluded, 1ull);
         }
         double2 u = make_double2(0.0, 0.0);
-        if (hw >= omega_cut) {
-          double f = sqrt(cph / (2.0 * mode_mass[i] * hw));
+        if (hw >= o.omega_cut) {
+          double f = sqrt(o.cph / (2.0 * o.mode_mass[i] * hw));
           u = make_double2(v.x * f, v.y * f);
         }
-        evec[(kk * n + rank) * n + i] = u;  // evec[q][nu][mu] = u_{mu nu}
+        o.evec[(kk * n + rank) * n + i] = u;  // evec[q][nu][mu] = u_{mu nu}
       }
     }
     if (mode == 0) {
@@ -233,14 +205,179 @@ __global__ __launch_bounds__(64) void bloch_eig_kernel(int mode, int n, int N, i
           rk += (wo < wc) || (wo == wc && jj < col);
         }
         if (live && e == 0) {
-          double *vo = vel + (kl * n + rk) * 3;
-          vo[0] = c0 * vel_unit;
-          vo[1] = c1 * vel_unit;
-          vo[2] = c2 * vel_unit;
+          double *vo = o.vel + (kl * n + rk) * 3;
+          vo[0] = c0 * o.vel_unit;
+          vo[1] = c1 * o.vel_unit;
+          vo[2] = c2 * o.vel_unit;
         }
       }
     }
-    __syncthreads();
+  __syncthreads();
+}
+
+template <int NP>
+__global__ __launch_bounds__(64) void bloch_eig_kernel(EigOut o, int N, int64_t k0, int64_t nk, int nr,
+                                                       const int *__restrict__ R, const double *__restrict__ w,
+                                                       const double *__restrict__ Rcart,
+                                                       const double2 *__restrict__ M,
+                                                       const double2 *__restrict__ tab) {
+  constexpr int L = NP * NP;
+  constexpr int MPW = 64 / L;
+  __shared__ double2 sA[64];
+  __shared__ double2 sV[64];
+  __shared__ Rot sR[64];
+  __shared__ double sW[64];
+  const int mode = o.mode, n = o.n;
+  const int lane = threadIdx.x;
+  const int mloc = lane / L;
+  const int e = lane % L;
+  const int i = e / NP, j = e % NP;
+  const bool valid_ij = (i < n) && (j < n);
+
+  const int64_t ngroups = (nk + MPW - 1) / MPW;
+  for (int64_t gidx = blockIdx.x; gidx < ngroups; gidx += gridDim.x) {
+    const int64_t kl = gidx * MPW + mloc;
+    const bool live = kl < nk;
+    const int64_t kg = k0 + (live ? kl : 0);
+    const int64_t k1 = kg % N, k2 = (kg / N) % N, k3 = kg / ((int64_t)N * N);
+
+    // ---- Bloch sum (and derivatives for electrons), direct over the R list ----
+    double2 acc = make_double2(0.0, 0.0);
+    double2 d0 = acc, d1 = acc, d2 = acc;
+    if (valid_ij) {
+      for (int r = 0; r < nr; r++) {
+        int64_t s = (k1 * R[3 * r] + k2 * R[3 * r + 1] + k3 * R[3 * r + 2]) % N;
+        if (s < 0) s += N;
+        double2 ph = tab[s];
+        double wr = w[r];
+        ph.x *= wr;
+        ph.y *= wr;
+        double2 t = cmul(ph, M[(size_t)r * n * n + i * n + j]);
+        acc = cadd(acc, t);
+        if (mode == 0) {
+          // i * R_a * t
+          double2 it = make_double2(-t.y, t.x);
+          double r0 = Rcart[3 * r], r1 = Rcart[3 * r + 1], r2 = Rcart[3 * r + 2];
+          d0.x += r0 * it.x; d0.y += r0 * it.y;
+          d1.x += r1 * it.x; d1.y += r1 * it.y;
+          d2.x += r2 * it.x; d2.y += r2 * it.y;
+        }
+      }
+    }
+    eig_store<NP>(o, live, kl, acc, d0, d1, d2, sA, sV, sR, sW);
+  }
+}
+
+// Separable form of the same Bloch sum for R lists that fill a box
+// [lo, lo + nb) (missing vectors are zero in the dense copy Mb, weights
+// folded in).  One wave per k-line (k2, k3): every lane first sums its
+// element over the (R2, R3) planes for each R1,
+//   T0(R1) = sum_{R2,R3} e^{i2pi(k2 R2 + k3 R3)/N} M(R),  T2, T3 the same
+//   weighted by R2, R3 (electrons),
+// in registers, then per k1 on the line
+//   M(k) = sum_R1 e^{i2pi k1 R1/N} T0(R1),  S1 = sum_R1 R1 e^{..} T0(R1),
+//   S2, S3 = sum_R1 e^{..} T2,3(R1),  dM/dk_a = i sum_b L_ba S_b
+// (L the lattice vectors as rows), which is the direct sum associated
+// differently.  NR1 bounds the box length along R1.
+struct BoxArgs {
+  int lo[3], nb[3];
+  double lat[9];
+};
+
+template <int NP, int NR1, int MODE>
+__global__ __launch_bounds__(64) void bloch_line_kernel(EigOut o, int N, BoxArgs bx, const double2 *__restrict__ Mb,
+                                                        const double2 *__restrict__ tab) {
+  constexpr int NRD = MODE == 0 ? NR1 : 1;  // derivative planes only for electrons
+  constexpr int L = NP * NP;
+  constexpr int MPW = 64 / L;
+  __shared__ double2 sA[64];
+  __shared__ double2 sV[64];
+  __shared__ Rot sR[64];
+  __shared__ double sW[64];
+  constexpr int mode = MODE;
+  const int n = o.n;
+  const int lane = threadIdx.x;
+  const int mloc = lane / L;
+  const int e = lane % L;
+  const int i = e / NP, j = e % NP;
+  const bool valid_ij = (i < n) && (j < n);
+  const int n1 = bx.nb[0], n2 = bx.nb[1], n3 = bx.nb[2];
+  const size_t nn = (size_t)n * n;
+  const int64_t nlines = (int64_t)N * N;
+  for (int64_t line = blockIdx.x; line < nlines; line += gridDim.x) {
+    const int k2 = (int)(line % N), k3 = (int)(line / N);
+    double2 T0[NR1], T2[NRD], T3[NRD];
+#pragma unroll
+    for (int b = 0; b < NR1; b++) T0[b] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < NRD; b++) T2[b] = T3[b] = make_double2(0.0, 0.0);
+    if (valid_ij) {
+      int i2 = imod(k2 * bx.lo[1], N);
+      const int i3s = imod(k3 * bx.lo[2], N);
+      for (int b2 = 0; b2 < n2; b2++) {
+        const double r2 = (double)(bx.lo[1] + b2);
+        int i23 = i2 + i3s;
+        i23 -= (i23 >= N) ? N : 0;
+        for (int b3 = 0; b3 < n3; b3++) {
+          const double2 ph = tab[i23];
+          const double r3 = (double)(bx.lo[2] + b3);
+          const double2 *m = Mb + ((size_t)b2 * n3 + b3) * nn + i * n + j;
+#pragma unroll
+          for (int b1 = 0; b1 < NR1; b1++) {
+            if (b1 < n1) {
+              const double2 t = cmul(ph, m[(size_t)b1 * n2 * n3 * nn]);
+              T0[b1] = cadd(T0[b1], t);
+              if constexpr (MODE == 0) {
+                T2[b1].x = fma(r2, t.x, T2[b1].x);
+                T2[b1].y = fma(r2, t.y, T2[b1].y);
+                T3[b1].x = fma(r3, t.x, T3[b1].x);
+                T3[b1].y = fma(r3, t.y, T3[b1].y);
+              }
+            }
+          }
+          i23 += k3;
+          i23 -= (i23 >= N) ? N : 0;
+        }
+        i2 += k2;
+        i2 -= (i2 >= N) ? N : 0;
+      }
+    }
+    for (int kb = 0; kb < N; kb += MPW) {
+      const int k1r = kb + mloc;
+      const bool live = k1r < N;
+      const int k1 = live ? k1r : 0;
+      double2 acc = make_double2(0.0, 0.0), s1 = acc, s2 = acc, s3 = acc;
+      if (valid_ij) {
+        int i1 = imod(k1 * bx.lo[0], N);
+#pragma unroll
+        for (int b1 = 0; b1 < NR1; b1++) {
+          if (b1 < n1) {
+            const double2 ph = tab[i1];
+            const double2 t = cmul(ph, T0[b1]);
+            acc = cadd(acc, t);
+            if constexpr (MODE == 0) {
+              const double r1 = (double)(bx.lo[0] + b1);
+              s1.x = fma(r1, t.x, s1.x);
+              s1.y = fma(r1, t.y, s1.y);
+              s2 = cadd(s2, cmul(ph, T2[b1]));
+              s3 = cadd(s3, cmul(ph, T3[b1]));
+            }
+            i1 += k1;
+            i1 -= (i1 >= N) ? N : 0;
+          }
+        }
+      }
+      double2 d[3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        // i * sum_b L_ba S_b
+        const double re = bx.lat[a] * s1.x + bx.lat[3 + a] * s2.x + bx.lat[6 + a] * s3.x;
+        const double im = bx.lat[a] * s1.y + bx.lat[3 + a] * s2.y + bx.lat[6 + a] * s3.y;
+        d[a] = make_double2(-im, re);
+      }
+      const int64_t kl = (int64_t)k1 + (int64_t)N * line;
+      eig_store<NP>(o, live, kl, acc, d[0], d[1], d[2], sA, sV, sR, sW);
+    }
   }
 }
 
@@ -266,13 +403,13 @@ hipError_t launch_bloch_eig(int mode, int n, int N, int64_t k0, int64_t nk, int 
                             double *eval, double2 *evec, double *vel, unsigned long long *n_excluded,
                             hipStream_t st) {
   if (nk <= 0) return hipSuccess;
+  const EigOut o{mode, n, mode_mass, cph, omega_cut, vel_unit, eval, evec, vel, n_excluded};
   int NP = n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8;
   int mpw = 64 / (NP * NP);
   int64_t ngroups = (nk + mpw - 1) / mpw;
   int grid = (int)(ngroups < 262144 ? ngroups : 262144);
-#define EPH_LAUNCH_BE(NPV)                                                                               \
-  hipLaunchKernelGGL(bloch_eig_kernel<NPV>, dim3(grid), dim3(64), 0, st, mode, n, N, k0, nk, nr, R, w, \
-                     Rcart, M, tab, mode_mass, cph, omega_cut, vel_unit, eval, evec, vel, n_excluded)
+#define EPH_LAUNCH_BE(NPV) \
+  hipLaunchKernelGGL(bloch_eig_kernel<NPV>, dim3(grid), dim3(64), 0, st, o, N, k0, nk, nr, R, w, Rcart, M, tab)
   switch (NP) {
     case 1: EPH_LAUNCH_BE(1); break;
     case 2: EPH_LAUNCH_BE(2); break;
@@ -281,6 +418,39 @@ hipError_t launch_bloch_eig(int mode, int n, int N, int64_t k0, int64_t nk, int 
   }
 #undef EPH_LAUNCH_BE
   return hipGetLastError();
+}
+
+hipError_t launch_bloch_lines(int mode, int n, int N, const int *lo, const int *nb, const double *lattice,
+                              const double2 *Mb, const double2 *tab, const double *mode_mass, double cph,
+                              double omega_cut, double vel_unit, double *eval, double2 *evec, double *vel,
+                              unsigned long long *n_excluded, hipStream_t st) {
+  const EigOut o{mode, n, mode_mass, cph, omega_cut, vel_unit, eval, evec, vel, n_excluded};
+  if (nb[0] > kBoxMaxR1) return hipErrorInvalidValue;
+  BoxArgs bx;
+  for (int a = 0; a < 3; a++) {
+    bx.lo[a] = lo[a];
+    bx.nb[a] = nb[a];
+  }
+  for (int a = 0; a < 9; a++) bx.lat[a] = lattice[a];
+  const int NP = n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8;
+  const int64_t nlines = (int64_t)N * N;
+  const int grid = (int)(nlines < 262144 ? nlines : 262144);
+#define EPH_LAUNCH_BL(NPV, R1)                                                                               \
+  if (mode == 0) hipLaunchKernelGGL((bloch_line_kernel<NPV, R1, 0>), dim3(grid), dim3(64), 0, st, o, N, bx, Mb, tab); \
+  else hipLaunchKernelGGL((bloch_line_kernel<NPV, R1, 1>), dim3(grid), dim3(64), 0, st, o, N, bx, Mb, tab);       \
+  return hipGetLastError();
+#define EPH_LAUNCH_NP(R1)        \
+  switch (NP) {                  \
+    case 1: EPH_LAUNCH_BL(1, R1) \
+    case 2: EPH_LAUNCH_BL(2, R1) \
+    case 4: EPH_LAUNCH_BL(4, R1) \
+    default: EPH_LAUNCH_BL(8, R1) \
+  }
+  if (nb[0] <= 7) EPH_LAUNCH_NP(7)
+  if (nb[0] <= 9) EPH_LAUNCH_NP(9)
+  EPH_LAUNCH_NP(kBoxMaxR1)
+#undef EPH_LAUNCH_NP
+#undef EPH_LAUNCH_BL
 }
 
 }  // namespace eph

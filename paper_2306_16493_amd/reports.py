@@ -159,7 +159,8 @@ def surrogate(workload_name="al_fcc_200", train_frac=0.02, chunks=8, threshold=0
 
 
 def surrogate_sweep(workload_name="al_fcc_200", train_fracs=(0.02, 0.05), thresholds=(0.01, 0.02, 0.05),
-                    members=5, steps=3000, seed=1649307, grid=None, precision="fp32", ref=None, chunks=8):
+                    members=5, steps=30000, batch=512, decay=True, seed=1649307, grid=None, precision="fp32",
+                    ref=None, chunks=8):
     """The surrogate over training fractions and spread thresholds against
     one full plain run.  The plain run (unless `ref` gives its sigma and
     time) is timed over disjoint k-point chunks; the table time every chunk
@@ -179,7 +180,7 @@ def surrogate_sweep(workload_name="al_fcc_200", train_fracs=(0.02, 0.05), thresh
     temps = list(w.temps)
     P = lambda ks: ctx.params(N, mu, temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision=precision, k_subset=ks)
     out = {"report": "surrogate_sweep", "workload": w.name, "grid": N, "precision": precision, "members": members,
-           "train_steps": steps, "settings": []}
+           "train_steps": steps, "batch": batch, "lr_decay": list(sg.DECAY) if decay else None, "settings": []}
     if ref is None:
         ctx.set_profiling(True)
         sk, sn, se, sv = ctx.select_states(P(None))
@@ -206,7 +207,7 @@ def surrogate_sweep(workload_name="al_fcc_200", train_fracs=(0.02, 0.05), thresh
     scale = np.max(np.abs(sig_ref))
     for tf in train_fracs:
         f = sg.fit(ctx, N, mu, temps, w.eta, lo, hi, w.band_lo, w.band_hi, train_frac=tf, members=members,
-                   steps=steps, seed=seed, precision=precision, log=_log)
+                   steps=steps, batch=batch, seed=seed, precision=precision, log=_log, decay=decay)
         for th in thresholds:
             r = sg.finish(f, th, log=_log)
             sk, sn, se, sv = r.states

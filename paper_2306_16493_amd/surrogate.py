@@ -58,8 +58,12 @@ class Fitted:
     times: dict
 
 
+# step decay of the learning rate: (fraction of the steps, factor on lr)
+DECAY = ((0.5, 1.0), (0.25, 0.25), (0.125, 1.0 / 16), (0.125, 1.0 / 64))
+
+
 def fit(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_frac=0.02, members=5,
-        steps=2000, batch=256, lr=2e-3, seed=1649307, precision="fp64", log=None):
+        steps=2000, batch=256, lr=2e-3, seed=1649307, precision="fp64", log=None, decay=False):
     import torch
     from .eph import Mlp
 
@@ -91,7 +95,11 @@ def fit(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_
     t2 = time.perf_counter()
     mlp = Mlp(ctx, members=members, n_out=nt, seed=seed)
     x_tr, y_tr = mlp.features(tr.state_k, tr.energy, tr.vel, grid, mu, inv_tau=tr.inv_tau)
-    loss = mlp.train(x_tr, y_tr, steps=steps, batch=batch, lr=lr)
+    if decay:  # Adam's moments carry over between the segments
+        for frac, fac in DECAY:
+            loss = mlp.train(x_tr, y_tr, steps=max(1, int(round(frac * steps))), batch=batch, lr=lr * fac)
+    else:
+        loss = mlp.train(x_tr, y_tr, steps=steps, batch=batch, lr=lr)
     torch.cuda.synchronize()
     times["fit_s"] = time.perf_counter() - t2
     say(f"[surrogate] member losses {np.array2string(loss, precision=4)}")
@@ -145,10 +153,10 @@ def finish(f, threshold=0.01, log=None, fallback_chunk=400000):
 
 def run(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo=0, band_hi=-1, train_frac=0.02, members=5,
         steps=2000, batch=256, lr=2e-3, threshold=0.01, seed=1649307, precision="fp64", log=None,
-        fallback_chunk=400000):
+        fallback_chunk=400000, decay=False):
     """Steps 1-6 for one threshold."""
     f = fit(ctx, grid, mu, temps, eta, win_lo, win_hi, band_lo, band_hi, train_frac, members, steps, batch, lr,
-            seed, precision, log)
+            seed, precision, log, decay)
     try:
         return finish(f, threshold, log, fallback_chunk)
     finally:

@@ -199,6 +199,9 @@ def make_system(name: str, seed: Optional[int] = None, real_g: bool = False) -> 
     'box5_w4', 'box446_w2a2'
               small models whose Rp set is a 5^3 box (4 orbitals, 1 atom)
               or a 4 x 4 x 6 box (2 orbitals, 2 atoms)
+    'chain_w2' 2 orbitals with hopping up to 7 cells along a1 (and nearest
+              neighbours along a2, a3): an H(R) list whose bounding box is
+              too long and too sparse for the separable Bloch sum
     'degen_w4', 'degen_w4_sym'
               exactly degenerate model: H(R) = h(R) (x) I_2 with a random
               2-orbital h (every band 2-fold), one atom with isotropic
@@ -208,7 +211,8 @@ def make_system(name: str, seed: Optional[int] = None, real_g: bool = False) -> 
     """
     defaults = {"toy_sc": 1649301, "al_fcc": 1649302, "si_fcc": 1649303,
                 "mini_w1": 1649311, "mini_w2a2": 1649312, "mini_w8": 1649313, "mini_w4a2": 1649314,
-                "box5_w4": 1649315, "box446_w2a2": 1649316, "degen_w4": 1649317, "degen_w4_sym": 1649317}
+                "box5_w4": 1649315, "box446_w2a2": 1649316, "degen_w4": 1649317, "degen_w4_sym": 1649317,
+                "chain_w2": 1649318}
     if seed is None:
         seed = defaults[name]
     rng = np.random.default_rng(seed)
@@ -254,6 +258,19 @@ def make_system(name: str, seed: Optional[int] = None, real_g: bool = False) -> 
         ham = _draw_ham(rng, lat, rh, nw)
         ifc = _draw_ifc(rng, lat, tau, mass, rd, rd_w, 0.040)
         gw = _draw_g(rng, lat, re, rp, 3 * mass.shape[0], nw)
+        i0 = int(np.where((rh == 0).all(axis=1))[0][0])
+        return System(name, lat, tau, mass, nw, rh, rh_w, ham, rd, rd_w, ifc, re, rp, gw,
+                      float(np.real(np.trace(ham[i0]))) / nw)
+    elif name == "chain_w2":
+        lat, tau, mass, nw = _sc(3.0), np.zeros((1, 3)), np.array([26.98]), 2
+        rh = np.array([[r, 0, 0] for r in range(-7, 8)] + [[0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]],
+                      dtype=np.int32)
+        rh_w = np.ones(rh.shape[0])
+        ham = _draw_ham(rng, _sc(1.0), rh, nw)  # decay over 1 A per cell: the long hops stay visible
+        rd, rd_w = ws_block(4)
+        ifc = _draw_ifc(rng, lat, tau, mass, rd, rd_w, 0.040)
+        re, rp = lattice_block(4), lattice_block(4)
+        gw = _draw_g(rng, lat, re, rp, 3, nw)
         i0 = int(np.where((rh == 0).all(axis=1))[0][0])
         return System(name, lat, tau, mass, nw, rh, rh_w, ham, rd, rd_w, ifc, re, rp, gw,
                       float(np.real(np.trace(ham[i0]))) / nw)

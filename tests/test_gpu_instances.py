@@ -11,7 +11,7 @@ import re
 import numpy as np
 import pytest
 
-from gpu_helpers import log, params_for, gpu_run, compare_rates, rel_err
+from gpu_helpers import log, params_for, gpu_run, compare_rates, rel_err, degenerate_mask
 from synth import make_system, workload
 from oracle import Oracle
 
@@ -223,4 +223,32 @@ def test_line_limit_unsupported(torch_cuda):
     with pytest.raises(EphError) as ei:
         ctx.count_states(ctx.params(257, s.mu_centroid, [300.0], 0.02, -1e3, 1e3))
     assert ei.value.code == EPH_E_UNSUPPORTED
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,N", [("chain_w2", 7), ("al_fcc", 6), ("si_fcc", 5)])
+def test_grid_tables_both_bloch_forms(torch_cuda, name, N):
+    """Band energies, velocities and rates against the oracle for the two
+    forms of the Bloch sum: chain_w2's H(R) list (hopping along a1 up to 7
+    cells, nearest neighbours along a2, a3) is too long and sparse for the
+    separable form and takes the direct sum over the list, while its D(R),
+    and H(R) and D(R) of the Al-like and Si-like models, fill their boxes
+    and take the separable form."""
+    from paper_2306_16493_amd import Context
+    s = make_system(name)
+    eta, temps = 0.05, [300.0]
+    mu = s.mu_centroid
+    ctx = Context(s)
+    p = ctx.params(N, mu, temps, eta, -1e3, 1e3)
+    g = gpu_run(ctx, p)
+    r = Oracle(s).run(N, mu, temps, eta, -1e3, 1e3)
+    assert np.array_equal(g["state_k"], r["state_k"]) and np.array_equal(g["state_n"], r["state_n"])
+    e_err = rel_err(g["energy"], r["energy"])
+    v_err = float(np.max(np.abs(g["vel"] - r["vel"])) / np.abs(r["vel"]).max())
+    log(f"[tables] {name} N={N}: {len(r['state_k'])} states, energy err {e_err:.2e}, velocity err {v_err:.2e}")
+    assert e_err < TOL
+    # velocities are gauge-invariant away from degeneracies; compare there
+    nd = ~degenerate_mask(r["tables"][0], r["state_k"], r["state_n"])
+    assert np.max(np.abs(g["vel"][nd] - r["vel"][nd])) <= TOL * np.abs(r["vel"]).max()
+    compare_rates(g, r["inv_tau"], r["tables"][0], r["state_k"], r["state_n"])
     ctx.close()
