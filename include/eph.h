@@ -148,7 +148,11 @@ typedef struct {
                                tables, state lists, per-batch buffers);
                                the states are processed in batches sized
                                to fit.  0 = automatic (per-batch buffers up
-                               to 8 GiB).  EPH_E_NOMEM, with the required
+                               to the free device memory less 8 GiB, at
+                               least 8 and at most 64 GiB; 8 GiB when
+                               transition rates are built; the context
+                               keeps them for later calls until
+                               eph_free).  EPH_E_NOMEM, with the required
                                size in eph_last_error, when the tables and
                                one group of states do not fit. */
   void *stream;             /* hipStream_t, NULL = default stream */

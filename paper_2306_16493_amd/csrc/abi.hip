@@ -538,7 +538,16 @@ static int32_t rates_impl(eph_ctx *c, const eph_rates_params *p, int64_t capacit
                                         std::to_string(gmax) + " states per group)");
       max_states = (int64_t)(((size_t)p->mem_budget_bytes - ws.fixed) / ws.per_state);
     } else {
-      max_states = std::max<int64_t>(gmax, (int64_t)(((size_t)8 << 30) / ws.per_state));
+      // automatic: the per-batch buffers take the free device memory less
+      // 8 GiB, between 8 and 64 GiB (8 GiB when transition rates are built,
+      // whose placement below assumes it), so that on a 288 GB part the
+      // states of a large grid need few batches and few launch tails
+      size_t xcap = (size_t)8 << 30;
+      size_t freeb = 0, totalb = 0;
+      if (!gr && hipMemGetInfo(&freeb, &totalb) == hipSuccess && freeb > ((size_t)16 << 30))
+        xcap = std::min<size_t>(freeb - ((size_t)8 << 30), (size_t)64 << 30);
+      (void)hipGetLastError();
+      max_states = std::max<int64_t>(gmax, (int64_t)(xcap / ws.per_state));
     }
     EPH_HIP(c, c->grp_tmp.ensure(sizeof(int64_t) * 2 * (ns + 1)));
     int64_t *flag = c->grp_tmp.as<int64_t>(), *pos = flag + ns + 1;

@@ -99,7 +99,7 @@ def precision(workload_name="si_fcc_150", subset_frac=0.01, seed=1649307, grid=N
 
 
 def surrogate(workload_name="al_fcc_200", train_frac=0.02, chunks=8, threshold=0.01, members=5,
-              steps=3000, seed=1649307, grid=None, precision="fp64"):
+              steps=30000, batch=512, decay=True, seed=1649307, grid=None, precision="fp64"):
     """The surrogate run, then the plain kernel on every k point the
     surrogate did not already compute with it (the full plain run is the
     union of these disjoint k-subset runs: its 1/tau is the reference and its
@@ -119,7 +119,7 @@ def surrogate(workload_name="al_fcc_200", train_frac=0.02, chunks=8, threshold=0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     r = sg.run(ctx, N, mu, temps, w.eta, lo, hi, w.band_lo, w.band_hi, train_frac=train_frac, members=members,
-               steps=steps, threshold=threshold, seed=seed, precision=precision, log=_log)
+               steps=steps, batch=batch, threshold=threshold, seed=seed, precision=precision, log=_log, decay=decay)
     torch.cuda.synchronize()
     t_sur = time.perf_counter() - t1
     _log(f"[surrogate] surrogate run {t_sur:.1f} s: {r.times}")
