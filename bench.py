@@ -145,7 +145,7 @@ def main():
                     help="form of the headline: auto (the fastest within 1e-3 relative sigma error of the FP64 "
                          "run), fp64, fp32 or bf16x3")
     ap.add_argument("--cpu-sample", type=int, default=40, help="k points of the oracle sample (0 = skip)")
-    ap.add_argument("--report", choices=["precision", "surrogate", "surrogate-sweep", "ablation"], default=None,
+    ap.add_argument("--report", choices=["precision", "surrogate", "surrogate-sweep", "ablation", "full"], default=None,
                     help="instead of the bench line, measure the FP32/BF16x3 forms or the surrogate on "
                          "their own workloads (one JSON line)")
     ap.add_argument("--subset-frac", type=float, default=0.01, help="k-point fraction of --report precision")
@@ -194,6 +194,11 @@ def main():
         prec = args.precision if args.precision != "auto" else "fp32"
         print(json.dumps(reports.surrogate_sweep(args.workload or "al_fcc_200", fr, th, grid=args.grid,
                                                  precision=prec, ref=ref)), flush=True)
+        return
+    if args.report == "full":
+        from paper_2306_16493_amd import reports
+        forms = ("fp32", "fp64") if args.precision == "auto" else (args.precision,)
+        print(json.dumps(reports.full_run(args.workload or "si_fcc_150", forms, grid=args.grid)), flush=True)
         return
     if args.report == "ablation":
         from paper_2306_16493_amd import reports

@@ -199,11 +199,11 @@ void rates_wave_kernel(RatesArgs a) {
 
   // final-state line energies: the next q-line's are loaded into registers
   // while the current one (in LDS, [m][p1]) is scanned
-  // lines are prefetched into registers while a line is worked on up to 1024
-  // energies in FP32 and 512 in FP64 (where registers are scarcer); longer
-  // ones are copied at the staging point, since the prefetch registers would
-  // push the kernel into spilling
-  constexpr bool PF = LPL <= (sizeof(T) == 8 ? 8 : 16);
+  // lines of up to 512 energies are prefetched into registers while a line
+  // is worked on; longer ones are copied at the staging point, since their
+  // prefetch registers would push the kernel into spilling (measured: the
+  // FP32 instance for 1024 energies is faster without them)
+  constexpr bool PF = LPL <= 8;
   constexpr int LPR = PF ? LPL : 1;
   LT nxt[LPR];
   const LT *eline;  // energy table the prefilter reads (FP64, or its float copy for long lines)

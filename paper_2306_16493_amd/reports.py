@@ -228,6 +228,61 @@ def surrogate_sweep(workload_name="al_fcc_200", train_fracs=(0.02, 0.05), thresh
     return out
 
 
+def full_run(workload_name="si_fcc_150", precisions=("fp32", "fp64"), chunks=10, grid=None):
+    """One form over every window state of a workload: the plain rates call
+    over disjoint k-point chunks (so that each call ends within a minute or
+    so and reports), then sigma from all of them.  Per form: the sum of the
+    chunk calls less the grid-table time that every chunk after the first
+    repeats, pairs per second, sigma, and sigma's error against the first
+    form."""
+    import torch
+    from synth import make_system, workload
+    from .eph import Context, merge_rates
+    w = workload(workload_name, grid)
+    s = make_system(w.system)
+    ctx = Context(s, device=0)
+    N = w.grid
+    mu, lo, hi = window(ctx, s, w, N)
+    temps = list(w.temps)
+    out = {"report": "full", "workload": w.name, "grid": N, "forms": {}}
+    ctx.set_profiling(True)
+    P = lambda prec, ks: ctx.params(N, mu, temps, w.eta, lo, hi, w.band_lo, w.band_hi, precision=prec, k_subset=ks)
+    sk, sn, se, sv = ctx.select_states(P("fp64", None))
+    kall = np.unique(sk.cpu().numpy())
+    out["n_states"] = int(sk.shape[0])
+    out["k_points"] = int(kall.size)
+    parts = [x for x in np.array_split(kall, chunks) if x.size]
+    sig0 = None
+    for prec in precisions:
+        inv = torch.zeros((len(temps), sk.shape[0]), dtype=torch.float64, device=sk.device)
+        t_sum, t_tab, n_kq, rates_ms = 0.0, [], 0, 0.0
+        for i, ks in enumerate(parts):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, _ = ctx.scattering_rates(P(prec, ks))
+            torch.cuda.synchronize()
+            t_sum += time.perf_counter() - t0
+            st = ctx.stage_times()
+            t_tab.append(st["tables_ms"] / 1e3)
+            rates_ms += st["rates_ms"]
+            n_kq += int(res.counts["n_kq"])
+            merge_rates(ctx, sk, sn, inv, res.state_k, res.state_n, res.inv_tau)
+            _log(f"[full] {w.name} {prec} chunk {i + 1}/{len(parts)}: {res.counts['n_states']} states, {t_sum:.1f} s")
+        sig = ctx.conductivity(se, sv, inv.reshape(-1), mu, temps, N ** 3)
+        t = t_sum - sum(t_tab[1:])
+        row = {"call_s": t, "chunk_calls_s": t_sum, "rates_s": rates_ms / 1e3, "tables_s_per_call": float(np.mean(t_tab)),
+               "n_kq": n_kq, "pairs_per_s": n_kq / t, "sigma": sig.tolist()}
+        if sig0 is None:
+            sig0 = sig
+        else:
+            row["sigma_rel_err_vs_first"] = float(np.max(np.abs(sig - sig0)) / np.max(np.abs(sig0)))
+        out["forms"][prec] = row
+        _log(f"[full] {w.name} {prec}: {t:.1f} s, {n_kq / t:.3e} (k,q) pairs/s")
+        del inv
+    ctx.close()
+    return out
+
+
 def _budget_parts(ctx, N, mu, w, lo, hi):
     """(fixed bytes, bytes per state of a batch, states per group) of a rates
     call, from the minimum that too small a mem_budget_bytes reports."""
