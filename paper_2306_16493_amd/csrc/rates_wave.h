@@ -199,11 +199,12 @@ void rates_wave_kernel(RatesArgs a) {
 
   // final-state line energies: the next q-line's are loaded into registers
   // while the current one (in LDS, [m][p1]) is scanned
-  // lines of up to 512 energies are prefetched into registers while a line
-  // is worked on; longer ones are copied at the staging point, since their
-  // prefetch registers would push the kernel into spilling (measured: the
-  // FP32 instance for 1024 energies is faster without them)
-  constexpr bool PF = LPL <= 8;
+  // in FP64, lines of up to 512 energies are prefetched into registers while
+  // a line is worked on; longer lines, and every line in FP32, are copied at
+  // the staging point instead (measured faster: the FP32 instances spill
+  // with the prefetch registers, and at three waves per SIMD hide the
+  // staging loads)
+  constexpr bool PF = sizeof(T) == 8 && LPL <= 8;
   constexpr int LPR = PF ? LPL : 1;
   LT nxt[LPR];
   const LT *eline;  // energy table the prefilter reads (FP64, or its float copy for long lines)
