@@ -1,15 +1,21 @@
-"""Measurements of the two added forms on their own workloads (host-side
-orchestration only; every number comes from the HIP path through the C ABI).
+"""Measurements beside the bench line (host-side orchestration only; every
+number comes from the HIP path through the C ABI).
 
-precision(): the FP32 and split-BF16x3 forms against the FP64 GPU path (which
-    the parity tests tie to the FP64 oracle) on a seeded subset of the k
-    points that carry states: per-state 1/tau and sigma errors, and the
-    speedup of each form's rates call over the FP64 one.
-surrogate(): the MLP-ensemble surrogate with plain fallback against the full
-    plain run on the same grid (assembled from disjoint k-subset runs):
-    sigma error and end-to-end speedup.
+precision():       the FP32 and split-BF16x3 forms against the FP64 GPU path
+                   (which the parity tests tie to the FP64 oracle) on a
+                   seeded subset of the k points that carry states: per-state
+                   1/tau and sigma errors, and each form's speedup.
+surrogate():       the MLP-ensemble surrogate with plain fallback against the
+                   full plain run on the same grid: sigma error and
+                   end-to-end speedup.
+surrogate_sweep(): the same over training fractions and spread thresholds,
+                   against one full plain run.
+full_run():        one or two forms over every window state of a workload.
+ablation():        the k-batch order of the vertex and the state-batch size
+                   of the q-batch kernel (Sec. III.D, Sec. IV.C).
 
-Both print progress lines and return one dict (bench.py prints it as JSON).
+Each prints progress lines and returns one dict (bench.py prints it as
+JSON).
 """
 from __future__ import annotations
 
