@@ -12,8 +12,11 @@ Steps, each a C-ABI call:
      + eph_merge_rates             states whose spread exceeds the threshold
                                    (and the training states), merged in;
   6. eph_conductivity              sigma from the blended rates.
-The choice of k points (a seeded permutation of the k indices) is host-side
-bookkeeping of which work to do.
+fit() does steps 1-4 once; finish() does steps 4 (blend) to 6 for one
+threshold, so several thresholds can share one fit; run() chains them.
+The choice of k points (a seeded permutation of the k indices) and the
+learning-rate schedule (successive eph_mlp_train calls, which keep Adam's
+moments) are host-side bookkeeping of which work to do.
 """
 from __future__ import annotations
 
