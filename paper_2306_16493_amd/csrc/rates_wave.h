@@ -116,7 +116,7 @@ void rates_wave_kernel(RatesArgs a) {
   int *sKcnt = sKfirst + SMX;                         // [SMX] states of each k-slot
   int *sK1 = sKcnt + SMX;                             // [SMX] k1 of each k-slot
   int *sSlot = sK1 + SMX;                             // [NZ][2] (q2, line) of each Z slot
-  LT *sLine = reinterpret_cast<LT *>(misc + LY::misc_bytes());  // [NW][N] current line energies
+  LT *sLine = reinterpret_cast<LT *>(misc + LY::misc_bytes());  // [N][NW] current line energies
   uint2 *sV = reinterpret_cast<uint2 *>(misc + LY::misc_bytes() + LY::line_bytes(N));  // vertex queue
 
   for (int t = threadIdx.x; t < N; t += WPB * 64) sTab[t] = mk<T>((T)a.tab[t].x, (T)a.tab[t].y);
@@ -207,12 +207,21 @@ void rates_wave_kernel(RatesArgs a) {
   constexpr bool PF = sizeof(T) == 8 && LPL <= 8;
   constexpr int LPR = PF ? LPL : 1;
   LT nxt[LPR];
-  const LT *eline;  // energy table the prefilter reads (FP64, or its float copy for long lines)
-  eline = a.eps32;
+  const LT *eline = a.eps32;  // float copy of the band energies, the prefilter's input
+  // a line is kept in LDS as in the table, [p1][m], and copied with 16-byte
+  // accesses when a row is a whole number of float4
+  auto copy_line = [&](const LT *src) __attribute__((always_inline)) {
+    if constexpr (NW % 4 == 0) {
+      const float4 *s4 = reinterpret_cast<const float4 *>(src);
+      float4 *d4 = reinterpret_cast<float4 *>(sLine);
+      for (int e = lane; e < LN / 4; e += 64) d4[e] = s4[e];
+    } else {
+      for (int e = lane; e < LN; e += 64) sLine[e] = src[e];
+    }
+  };
   {
     const int l3 = (k3 + a.q3_lo >= N) ? k3 + a.q3_lo - N : k3 + a.q3_lo;
-    const LT *l0 = eline + (size_t)(k2 + N * l3) * LN;
-    for (int e = lane; e < LN; e += 64) sLine[(e % NW) * N + e / NW] = (LT)l0[e];
+    copy_line(eline + (size_t)(k2 + N * l3) * LN);
   }
 
   // One candidate = (k-slot, p1, Z slot): every state of that k point against
@@ -637,11 +646,22 @@ void rates_wave_kernel(RatesArgs a) {
           const int p1 = c0 + lane;
           unsigned bm = 0u;  // bands of this p1 inside the window
           if (p1 < N) {
+            float ev[NW];
+            if constexpr (NW % 4 == 0) {
 #pragma unroll
-            for (int m = 0; m < NW; m++) {
-              const float ev = sLine[m * N + p1];
-              bm |= ((ev >= lo_w) & (ev <= hi_w)) ? (1u << m) : 0u;
+              for (int v = 0; v < NW / 4; v++) {
+                const float4 f = reinterpret_cast<const float4 *>(sLine + (size_t)p1 * NW)[v];
+                ev[4 * v] = f.x;
+                ev[4 * v + 1] = f.y;
+                ev[4 * v + 2] = f.z;
+                ev[4 * v + 3] = f.w;
+              }
+            } else {
+#pragma unroll
+              for (int m = 0; m < NW; m++) ev[m] = sLine[p1 * NW + m];
             }
+#pragma unroll
+            for (int m = 0; m < NW; m++) bm |= ((ev[m] >= lo_w) & (ev[m] <= hi_w)) ? (1u << m) : 0u;
           }
           const bool any = bm != 0u;
           const unsigned long long bits = __ballot(any);
@@ -658,16 +678,16 @@ void rates_wave_kernel(RatesArgs a) {
         }
       }
       __syncwarp();
-      // stage the next line's energies ([m][p1] in LDS); the scan of this
-      // line is done, and the drains read energies from global memory
+      // stage the next line's energies; the scan of this line is done, and
+      // the drains read energies from global memory
       if constexpr (PF) {
 #pragma unroll
         for (int i = 0; i < LPL; i++) {
           const int e = lane + 64 * i;
-          if (e < LN) sLine[(e % NW) * N + e / NW] = (LT)nxt[i];
+          if (e < LN) sLine[e] = nxt[i];
         }
       } else {
-        for (int e = lane; e < LN; e += 64) sLine[(e % NW) * N + e / NW] = nline[e];
+        copy_line(nline);
       }
       __syncwarp();
     }
