@@ -9,7 +9,11 @@
 //   mlp_fwdbwd_kernel  one workgroup = one member x one tile of 32 samples:
 //                      forward through the layers with pre-activations kept
 //                      in LDS, backward, and the tile's gradient written to
-//                      its own slot (no atomics);
+//                      its own slot (no atomics).  The hidden 128 x 128
+//                      weights are staged in LDS (padded rows, loads of the
+//                      next layer's issued before the current one's sums) and
+//                      every thread owns a 4 x 4 (forward, input gradient) or
+//                      8 x 8 (weight gradient) block fed by float4 LDS reads;
 //   mlp_adam_kernel    per parameter: the tile gradients summed in tile
 //                      order, then the Adam update;
 //   mlp_forward_kernel inference for all members;
@@ -54,7 +58,9 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
   x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
   return x ^ (x >> 31);
 }
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+// logistic function with the hardware exponential and reciprocal (a few ulp;
+// the network is fit in FP32 to a target far coarser than that)
+__device__ __forceinline__ float sigm(float z) { return __fdividef(1.0f, 1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z) {
   const float s = sigm(z);
@@ -84,6 +90,13 @@ __device__ void dense_fwd(const float *__restrict__ W, const float *__restrict__
   }
 }
 
+// Training tile: TT samples per workgroup of TN threads (four waves).
+constexpr int TT = 32;
+constexpr int TN = 256;
+// Row pitch (floats) of activations, gradients and staged weights in LDS: a
+// column read by the 16 rows of an MFMA operand falls in distinct banks.
+constexpr int HP = H + 4;
+
 struct TrainArgs {
   int nout;
   int64_t n;             // training samples
@@ -92,128 +105,382 @@ struct TrainArgs {
   const float *params;   // [members][P]
   float *grad_part;      // [members][tiles][P]
   float *loss_part;      // [members][tiles]
-  int tiles;             // tiles per member (batch = tiles * TS)
+  int tiles;             // tiles per member (batch = tiles * TT)
   unsigned long long seed;
   long long step;        // -1: the batch is samples 0..batch-1 in order
 };
 
-__global__ __launch_bounds__(THREADS) void mlp_fwdbwd_kernel(TrainArgs a) {
-  __shared__ float sX[TS][NIN + 1];
-  __shared__ float sZ[3][TS][H];   // pre-activations of the hidden layers
-  __shared__ float sD[TS][H];      // gradient w.r.t. the current layer's pre-activation
-  __shared__ float sG[TS][H];      // gradient w.r.t. the previous layer's output
-  __shared__ float sH[TS][H];      // post-activation scratch
-  __shared__ float sDY[TS][MAXOUT];
-  __shared__ float sLoss[THREADS];
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ float comp(const float4 &v, int q) { return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w; }
+
+// FP32 matrix product D = A B + C on one 16 x 16 tile, K = 4:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 (l / 16) + q][l % 16], q < 4.  The hidden-layer sums run over blocks of
+// 16 inner indices; in a block, lane group g = l / 16 takes the indices
+// 16 kb + 4 g + r (r < 4) in four successive products, for both operands.
+__device__ __forceinline__ f4v mfma(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// One H x H weight matrix (row-major, any 4-byte alignment) from global
+// memory: coalesced loads into registers, then into LDS rows of pitch HP.
+struct WStage {
+  float v[H * H / TN];
+  __device__ __forceinline__ void load(const float *__restrict__ W) {
+#pragma unroll
+    for (int k = 0; k < H * H / TN; k++) v[k] = W[threadIdx.x + TN * k];
+  }
+  __device__ __forceinline__ void store(float *sW) const {
+#pragma unroll
+    for (int k = 0; k < H * H / TN; k++) {
+      const int f = threadIdx.x + TN * k;
+      sW[(f / H) * HP + f % H] = v[k];
+    }
+  }
+};
+
+// Tile ownership of the hidden-layer products: wave w, lane l, r16 = l % 16,
+// g = l / 16.  Forward and input gradient: the wave holds samples
+// 16 st + 4 g + q (st < 2) x columns 16 (2 w + ot) + r16 (ot < 2).
+struct Lane {
+  int w, r16, g;
+  __device__ Lane() : w(threadIdx.x >> 6), r16(threadIdx.x & 15), g((threadIdx.x >> 4) & 3) {}
+};
+
+// z[s][o] = b[o] + sum_i W[o][i] a[s][i]  (W staged in sW, a in sA)
+__device__ __forceinline__ void hidden_fwd(const Lane &L, const float *sW, const float *__restrict__ b,
+                                           const float *sA, f4v acc[2][2]) {
+#pragma unroll
+  for (int ot = 0; ot < 2; ot++) {
+    const float bo = b[16 * (2 * L.w + ot) + L.r16];
+#pragma unroll
+    for (int st = 0; st < 2; st++) acc[st][ot] = f4v{bo, bo, bo, bo};
+  }
+  for (int kb = 0; kb < H; kb += 16) {
+    float4 av[2], wv[2];
+#pragma unroll
+    for (int st = 0; st < 2; st++) av[st] = ld4(&sA[(16 * st + L.r16) * HP + kb + 4 * L.g]);
+#pragma unroll
+    for (int ot = 0; ot < 2; ot++) wv[ot] = ld4(&sW[(16 * (2 * L.w + ot) + L.r16) * HP + kb + 4 * L.g]);
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+      for (int st = 0; st < 2; st++)
+#pragma unroll
+        for (int ot = 0; ot < 2; ot++) acc[st][ot] = mfma(comp(av[st], r), comp(wv[ot], r), acc[st][ot]);
+  }
+}
+
+// g[s][i] = sum_o dz[s][o] W[o][i]  (W staged in sW, dz in sD)
+__device__ __forceinline__ void hidden_bwd_input(const Lane &L, const float *sW, const float *sD, f4v acc[2][2]) {
+#pragma unroll
+  for (int st = 0; st < 2; st++)
+#pragma unroll
+    for (int ot = 0; ot < 2; ot++) acc[st][ot] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int kb = 0; kb < H; kb += 16) {
+    float4 dv[2];
+    float wv[2][4];
+#pragma unroll
+    for (int st = 0; st < 2; st++) dv[st] = ld4(&sD[(16 * st + L.r16) * HP + kb + 4 * L.g]);
+#pragma unroll
+    for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) wv[ot][r] = sW[(kb + 4 * L.g + r) * HP + 16 * (2 * L.w + ot) + L.r16];
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+      for (int st = 0; st < 2; st++)
+#pragma unroll
+        for (int ot = 0; ot < 2; ot++) acc[st][ot] = mfma(comp(dv[st], r), wv[ot][r], acc[st][ot]);
+  }
+}
+
+// dW[o][i] = sum_s dz[s][o] a[s][i] over the tile's samples (the wave holds
+// rows 16 (2 w + ot) + 4 g + q x all columns), stored into the tile's slot;
+// db[o] = sum_s dz[s][o] (per lane over its samples, then across the four
+// lane groups).
+__device__ __forceinline__ void hidden_bwd_weights(const Lane &L, const float *sD, const float *sA,
+                                                   float *__restrict__ gW, float *__restrict__ gb) {
+  f4v acc[2][8];
+  float db[2] = {0.0f, 0.0f};
+#pragma unroll
+  for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+    for (int it = 0; it < 8; it++) acc[ot][it] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int kb = 0; kb < TT; kb += 16) {
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int s = kb + 4 * L.g + r;
+      float dv[2], av[8];
+#pragma unroll
+      for (int ot = 0; ot < 2; ot++) {
+        dv[ot] = sD[s * HP + 16 * (2 * L.w + ot) + L.r16];
+        db[ot] += dv[ot];
+      }
+#pragma unroll
+      for (int it = 0; it < 8; it++) av[it] = sA[s * HP + 16 * it + L.r16];
+#pragma unroll
+      for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+        for (int it = 0; it < 8; it++) acc[ot][it] = mfma(dv[ot], av[it], acc[ot][it]);
+    }
+  }
+#pragma unroll
+  for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+    for (int it = 0; it < 8; it++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) gW[(size_t)(16 * (2 * L.w + ot) + 4 * L.g + q) * H + 16 * it + L.r16] = acc[ot][it][q];
+#pragma unroll
+  for (int ot = 0; ot < 2; ot++) {
+    db[ot] += __shfl_xor(db[ot], 16);
+    db[ot] += __shfl_xor(db[ot], 32);
+    if (L.g == 0) gb[16 * (2 * L.w + ot) + L.r16] = db[ot];
+  }
+}
+
+__global__ __launch_bounds__(TN) void mlp_fwdbwd_kernel(TrainArgs a) {
+  __shared__ float sX[TT][NIN + 1];
+  __shared__ __align__(16) float sZ[3][TT * HP];  // pre-activations of the hidden layers
+  __shared__ __align__(16) float sA[TT * HP];     // input activations of the current layer
+  __shared__ __align__(16) float sD[TT * HP];     // gradient w.r.t. the current layer's pre-activation
+  __shared__ __align__(16) float sW[H * HP];      // the current hidden layer's weights
+  __shared__ __align__(16) float sW4[MAXOUT * H];  // output-layer weights
+  __shared__ float sDY[TT][MAXOUT];
+  __shared__ float sYT[TT][MAXOUT];               // targets of the tile's samples
+  __shared__ float sLoss[TN / 64];
+  __shared__ long long sIdx[TT];
   const int member = blockIdx.y, tile = blockIdx.x, t = threadIdx.x;
   const int nout = a.nout;
   const int64_t P = n_params(nout);
   const Offs of = offsets(nout);
   const float *prm = a.params + (size_t)member * P;
   float *gp = a.grad_part + ((size_t)member * a.tiles + tile) * P;
-  const float inv_batch = 1.0f / (float)(a.tiles * TS * nout);
+  const float inv_batch = 1.0f / (float)(a.tiles * TT * nout);
+  const Lane L;
 
   // minibatch sample indices
-  __shared__ long long sIdx[TS];
-  if (t < TS) {
+  if (t < TT) {
     long long idx;
-    if (a.step < 0) idx = (long long)tile * TS + t;
+    if (a.step < 0) idx = (long long)tile * TT + t;
     else {
       unsigned long long h = splitmix64(a.seed ^ splitmix64((unsigned long long)member * 0x100000001ull +
                                                             (unsigned long long)a.step * 0x9E37ull +
-                                                            (unsigned long long)(tile * TS + t)));
-      idx = (long long)(h % (unsigned long long)a.n);
+                                                            (unsigned long long)(tile * TT + t)));
+      idx = (long long)__umul64hi(h, (unsigned long long)a.n);  // uniform in [0, n)
     }
     sIdx[t] = idx;
   }
+  // first layer (NIN inputs) on the vector units: thread (og, sg) owns
+  // columns og + 32 j and samples 4 sg + u; its weight rows are loaded now
+  const int og = t & 31, sg = t >> 5;
+  float w1r[4][NIN + 1];
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+#pragma unroll
+    for (int i = 0; i < NIN; i++) w1r[j][i] = prm[of.w1 + (size_t)(og + 32 * j) * NIN + i];
+    w1r[j][NIN] = prm[of.b1 + og + 32 * j];
+  }
+  WStage ws;
+  ws.load(prm + of.w2);
   __syncthreads();
-  for (int e = t; e < TS * NIN; e += THREADS) {
+  for (int e = t; e < TT * NIN; e += TN) {
     const int s = e / NIN, i = e % NIN;
     const long long idx = sIdx[s];
     sX[s][i] = idx < a.n ? a.x[idx * NIN + i] : 0.0f;
   }
+  for (int e = t; e < nout * H; e += TN) sW4[e] = prm[of.w4 + e];
+  for (int e = t; e < TT * nout; e += TN) {
+    const long long idx = sIdx[e / nout];
+    sYT[e / nout][e % nout] = idx < a.n ? a.y[idx * nout + e % nout] : 0.0f;
+  }
   __syncthreads();
   // ---- forward ----
-  dense_fwd(prm + of.w1, prm + of.b1, &sX[0][0], NIN, NIN + 1, &sZ[0][0][0], H);
+  {
+    float z[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+#pragma unroll
+      for (int u = 0; u < 4; u++) z[u][j] = w1r[j][NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; i++)
+#pragma unroll
+        for (int u = 0; u < 4; u++) z[u][j] = fmaf(w1r[j][i], sX[4 * sg + u][i], z[u][j]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        sZ[0][(4 * sg + u) * HP + og + 32 * j] = z[u][j];
+        sA[(4 * sg + u) * HP + og + 32 * j] = silu(z[u][j]);
+      }
+  }
+  ws.store(sW);
   __syncthreads();
-  for (int e = t; e < TS * H; e += THREADS) sH[e / H][e % H] = silu(sZ[0][e / H][e % H]);
+  f4v acc[2][2];
+  // hidden activations written back from the product tiles
+  auto put = [&](float *z_out, const f4v (&v)[2][2]) {
+#pragma unroll
+    for (int st = 0; st < 2; st++)
+#pragma unroll
+      for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int e = (16 * st + 4 * L.g + q) * HP + 16 * (2 * L.w + ot) + L.r16;
+          z_out[e] = v[st][ot][q];
+          sA[e] = silu(v[st][ot][q]);
+        }
+  };
+  ws.load(prm + of.w3);
+  hidden_fwd(L, sW, prm + of.b2, sA, acc);
   __syncthreads();
-  dense_fwd(prm + of.w2, prm + of.b2, &sH[0][0], H, H, &sZ[1][0][0], H);
+  put(sZ[1], acc);
+  ws.store(sW);
   __syncthreads();
-  for (int e = t; e < TS * H; e += THREADS) sH[e / H][e % H] = silu(sZ[1][e / H][e % H]);
+  hidden_fwd(L, sW, prm + of.b3, sA, acc);
   __syncthreads();
-  dense_fwd(prm + of.w3, prm + of.b3, &sH[0][0], H, H, &sZ[2][0][0], H);
+  put(sZ[2], acc);
   __syncthreads();
-  for (int e = t; e < TS * H; e += THREADS) sH[e / H][e % H] = silu(sZ[2][e / H][e % H]);
-  __syncthreads();
-  // output layer and dL/dy (mean squared error over batch and outputs)
+  // output layer and dL/dy (mean squared error over batch and outputs):
+  // wave w < 2 takes samples 16 w + 4 g + q x outputs n = r16 (< nout) as
+  // one 16 x 16 tile over the 128 inputs
   float lsum = 0.0f;
-  for (int e = t; e < TS * nout; e += THREADS) {
-    const int s = e / nout, n = e % nout;
-    float yv = prm[of.b4 + n];
-    for (int i = 0; i < H; i++) yv = fmaf(prm[of.w4 + (size_t)n * H + i], sH[s][i], yv);
-    const long long idx = sIdx[s];
-    const float target = idx < a.n ? a.y[idx * nout + n] : yv;
-    const float d = yv - target;
-    sDY[s][n] = 2.0f * d * inv_batch;
-    lsum += d * d * inv_batch;
+  if (L.w < 2) {
+    f4v yv = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    const bool nv = L.r16 < nout;
+    for (int kb = 0; kb < H; kb += 16) {
+      const float4 av = ld4(&sA[(16 * L.w + L.r16) * HP + kb + 4 * L.g]);
+      const float4 w4 = ld4(&sW4[(nv ? L.r16 : 0) * H + kb + 4 * L.g]);
+      const float4 wv = nv ? w4 : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+      for (int r = 0; r < 4; r++) yv = mfma(comp(av, r), comp(wv, r), yv);
+    }
+    if (nv) {
+      const float bn = prm[of.b4 + L.r16];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int s = 16 * L.w + 4 * L.g + q;
+        const float y = yv[q] + bn;
+        const float d = sIdx[s] < a.n ? y - sYT[s][L.r16] : 0.0f;
+        sDY[s][L.r16] = 2.0f * d * inv_batch;
+        lsum += d * d * inv_batch;
+      }
+    }
   }
-  sLoss[t] = lsum;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+  if ((t & 63) == 0) sLoss[t >> 6] = lsum;
   __syncthreads();
-  if (t == 0) {
-    float l = 0.0f;
-    for (int i = 0; i < THREADS; i++) l += sLoss[i];
-    a.loss_part[(size_t)member * a.tiles + tile] = l;
-  }
+  if (t == 0) a.loss_part[(size_t)member * a.tiles + tile] = (sLoss[0] + sLoss[1]) + (sLoss[2] + sLoss[3]);
   // ---- backward ----
-  // W4, b4
-  for (int e = t; e < nout * (H + 1); e += THREADS) {
-    const int n = e / (H + 1), i = e % (H + 1);
-    float g = 0.0f;
-    for (int s = 0; s < TS; s++) g = fmaf(sDY[s][n], i < H ? sH[s][i] : 1.0f, g);
-    gp[i < H ? of.w4 + (size_t)n * H + i : of.b4 + n] = g;
+  {  // output layer on 16 x 16 tiles over this wave's columns
+     // i = 16 (2 w + ot) + r16: dW4[n][i] = sum_s dy[s][n] h3[s][i] (rows
+     // n >= nout are zero and not stored); dh3 = dy W4 (inner index n, one
+     // product per tile), dz3 = dh3 silu'(z3) into sD; then h2 into sA on the
+     // same columns (this wave's reads of h3 there are done)
+    f4v g4[2] = {f4v{0.0f, 0.0f, 0.0f, 0.0f}, f4v{0.0f, 0.0f, 0.0f, 0.0f}};
+    float b4 = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < TT; kb += 16)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int s = kb + 4 * L.g + r;
+        const float dv = L.r16 < nout ? sDY[s][L.r16 < nout ? L.r16 : 0] : 0.0f;
+        b4 += dv;
+#pragma unroll
+        for (int ot = 0; ot < 2; ot++) g4[ot] = mfma(dv, sA[s * HP + 16 * (2 * L.w + ot) + L.r16], g4[ot]);
+      }
+    if (L.g == 0) {
+#pragma unroll
+      for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          if (q < nout) gp[of.w4 + (size_t)q * H + 16 * (2 * L.w + ot) + L.r16] = g4[ot][q];
+    }
+    b4 += __shfl_xor(b4, 16);
+    b4 += __shfl_xor(b4, 32);
+    if (L.w == 0 && L.g == 0 && L.r16 < nout) gp[of.b4 + L.r16] = b4;
+#pragma unroll
+    for (int st = 0; st < 2; st++)
+#pragma unroll
+      for (int ot = 0; ot < 2; ot++) {
+        const int col = 16 * (2 * L.w + ot) + L.r16;
+        const f4v d = mfma(L.g < nout ? sDY[16 * st + L.r16][L.g] : 0.0f, L.g < nout ? sW4[L.g * H + col] : 0.0f,
+                           f4v{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int e = (16 * st + 4 * L.g + q) * HP + col;
+          sD[e] = d[q] * dsilu(sZ[2][e]);
+          sA[e] = silu(sZ[1][e]);
+        }
+      }
   }
-  // dL/dh3 -> dL/dz3
-  for (int e = t; e < TS * H; e += THREADS) {
-    const int s = e / H, i = e % H;
-    float g = 0.0f;
-    for (int n = 0; n < nout; n++) g = fmaf(sDY[s][n], prm[of.w4 + (size_t)n * H + i], g);
-    sD[s][i] = g * dsilu(sZ[2][s][i]);
-  }
+  // third hidden layer: the input gradient with W3 (still staged), then the
+  // weight gradients
+  ws.load(prm + of.w2);
   __syncthreads();
-  for (int layer = 2; layer >= 0; layer--) {
-    const int64_t ow = layer == 2 ? of.w3 : layer == 1 ? of.w2 : of.w1;
-    const int64_t ob = layer == 2 ? of.b3 : layer == 1 ? of.b2 : of.b1;
-    const int nin = layer == 0 ? NIN : H;
-    // input activations of this layer into sH
-    if (layer > 0) {
-      for (int e = t; e < TS * H; e += THREADS) sH[e / H][e % H] = silu(sZ[layer - 1][e / H][e % H]);
-    }
-    __syncthreads();
-    // weight and bias gradients: dW[o][i] = sum_s dz[s][o] in[s][i]
-    for (int e = t; e < H * (nin + 1); e += THREADS) {
-      const int o = e / (nin + 1), i = e % (nin + 1);
-      float g = 0.0f;
-      if (i < nin) {
-        for (int s = 0; s < TS; s++) g = fmaf(sD[s][o], layer > 0 ? sH[s][i] : sX[s][i], g);
-        gp[ow + (size_t)o * nin + i] = g;
-      } else {
-        for (int s = 0; s < TS; s++) g += sD[s][o];
-        gp[ob + o] = g;
+  hidden_bwd_input(L, sW, sD, acc);
+  hidden_bwd_weights(L, sD, sA, gp + of.w3, gp + of.b3);
+  __syncthreads();
+  // dz2 = g * silu'(z2) into sD, h1 into sA, W2 into sW
+#pragma unroll
+  for (int st = 0; st < 2; st++)
+#pragma unroll
+    for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int e = (16 * st + 4 * L.g + q) * HP + 16 * (2 * L.w + ot) + L.r16;
+        sD[e] = acc[st][ot][q] * dsilu(sZ[1][e]);
+        sA[e] = silu(sZ[0][e]);
       }
-    }
-    if (layer > 0) {
-      // dL/d(input) = W^T dz, then through the previous SiLU
-      for (int e = t; e < TS * H; e += THREADS) {
-        const int s = e / H, i = e % H;
-        float g = 0.0f;
-        for (int o = 0; o < H; o++) g = fmaf(sD[s][o], prm[ow + (size_t)o * H + i], g);
-        sG[s][i] = g * dsilu(sZ[layer - 1][s][i]);
+  ws.store(sW);
+  __syncthreads();
+  // second hidden layer
+  hidden_bwd_input(L, sW, sD, acc);
+  hidden_bwd_weights(L, sD, sA, gp + of.w2, gp + of.b2);
+  __syncthreads();
+#pragma unroll
+  for (int st = 0; st < 2; st++)
+#pragma unroll
+    for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int e = (16 * st + 4 * L.g + q) * HP + 16 * (2 * L.w + ot) + L.r16;
+        sD[e] = acc[st][ot][q] * dsilu(sZ[0][e]);
       }
-      __syncthreads();
-      for (int e = t; e < TS * H; e += THREADS) sD[e / H][e % H] = sG[e / H][e % H];
+  __syncthreads();
+  {  // first layer: dW1[o][i] = sum_s dz1[s][o] x[s][i] on 16 x 16 tiles
+     // (columns i >= NIN are zero and not stored), db1 as for the hidden layers
+    f4v w1[2] = {f4v{0.0f, 0.0f, 0.0f, 0.0f}, f4v{0.0f, 0.0f, 0.0f, 0.0f}};
+    float b1[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < TT; kb += 16)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int s = kb + 4 * L.g + r;
+        const float xv = L.r16 < NIN ? sX[s][L.r16 < NIN ? L.r16 : 0] : 0.0f;
+#pragma unroll
+        for (int ot = 0; ot < 2; ot++) {
+          const float dv = sD[s * HP + 16 * (2 * L.w + ot) + L.r16];
+          w1[ot] = mfma(dv, xv, w1[ot]);
+          b1[ot] += dv;
+        }
+      }
+    if (L.r16 < NIN) {
+#pragma unroll
+      for (int ot = 0; ot < 2; ot++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) gp[of.w1 + (size_t)(16 * (2 * L.w + ot) + 4 * L.g + q) * NIN + L.r16] = w1[ot][q];
     }
-    __syncthreads();
+#pragma unroll
+    for (int ot = 0; ot < 2; ot++) {
+      b1[ot] += __shfl_xor(b1[ot], 16);
+      b1[ot] += __shfl_xor(b1[ot], 32);
+      if (L.g == 0) gp[of.b1 + 16 * (2 * L.w + ot) + L.r16] = b1[ot];
+    }
   }
 }
 
@@ -476,7 +743,7 @@ int run_fwdbwd(eph_mlp *m, int64_t n, const float *x, const float *y, int tiles,
   a.tiles = tiles;
   a.seed = m->seed;
   a.step = step;
-  hipLaunchKernelGGL(mlp_fwdbwd_kernel, dim3(tiles, m->members), dim3(THREADS), 0, st, a);
+  hipLaunchKernelGGL(mlp_fwdbwd_kernel, dim3(tiles, m->members), dim3(TN), 0, st, a);
   MHIP(m, hipGetLastError());
   return EPH_OK;
 }
@@ -561,7 +828,7 @@ int32_t eph_mlp_features(eph_ctx *ctx, int64_t n, const int32_t *state_k, const 
 int32_t eph_mlp_train(eph_mlp *m, int64_t n, const float *x, const float *y, int32_t steps, int32_t batch,
                       float lr, void *stream, float *loss_host) {
   if (!m) return EPH_E_INVALID;
-  if (n < 1 || !x || !y || steps < 0 || batch < TS || batch % TS || !(lr > 0.0f))
+  if (n < 1 || !x || !y || steps < 0 || batch < TT || batch % TT || !(lr > 0.0f))
     return mfail(m, EPH_E_INVALID, "train: n >= 1, batch a positive multiple of 32, lr > 0");
   DeviceGuard dg(m->ctx->device);
   if (!dg.ok) return EPH_E_DEVICE;
@@ -576,7 +843,7 @@ int32_t eph_mlp_train(eph_mlp *m, int64_t n, const float *x, const float *y, int
   hipLaunchKernelGGL(mlp_apply_norm_kernel, dim3((unsigned)((n * NIN + 255) / 256)), dim3(256), 0, st, n, m->nout, x,
                      y, m->norm.as<float>(), m->xn.as<float>(), m->yn.as<float>());
   MHIP(m, hipGetLastError());
-  const int tiles = batch / TS;
+  const int tiles = batch / TT;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   const int64_t np = (int64_t)m->members * m->P;
   for (int s = 0; s < steps; s++) {
@@ -585,8 +852,8 @@ int32_t eph_mlp_train(eph_mlp *m, int64_t n, const float *x, const float *y, int
     if (r != EPH_OK) return r;
     const float bc1 = 1.0f - powf(b1, (float)m->step), bc2 = 1.0f - powf(b2, (float)m->step);
     hipLaunchKernelGGL(mlp_adam_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, m->members, tiles,
-                       m->P, m->gpart.as<float>(), m->params.as<float>(), m->m1.as<float>(), m->m2.as<float>(),
-                       (float *)nullptr, lr, b1, b2, eps, bc1, bc2, 1);
+                       m->P, m->gpart.as<float>(), m->params.as<float>(), m->m1.as<float>(),
+                       m->m2.as<float>(), (float *)nullptr, lr, b1, b2, eps, bc1, bc2, 1);
     MHIP(m, hipGetLastError());
   }
   if (loss_host) {
@@ -600,10 +867,10 @@ int32_t eph_mlp_train(eph_mlp *m, int64_t n, const float *x, const float *y, int
 
 int32_t eph_mlp_gradient(eph_mlp *m, int64_t n, const float *x, const float *y, float *grad_host,
                          float *loss_host) {
-  if (!m || n < TS || n % TS || !x || !y || !grad_host) return EPH_E_INVALID;
+  if (!m || n < TT || n % TT || !x || !y || !grad_host) return EPH_E_INVALID;
   DeviceGuard dg(m->ctx->device);
   if (!dg.ok) return EPH_E_DEVICE;
-  const int tiles = (int)(n / TS);
+  const int tiles = (int)(n / TT);
   int r = run_fwdbwd(m, n, x, y, tiles, -1, 0);
   if (r != EPH_OK) return r;
   const int64_t np = (int64_t)m->members * m->P;
