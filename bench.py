@@ -207,7 +207,8 @@ def main():
     if args.report == "surrogate":
         from paper_2306_16493_amd import reports
         wl = args.workload or "al_fcc_200"
-        print(json.dumps(reports.surrogate(wl, grid=args.grid, precision=args.precision)), flush=True)
+        prec = args.precision if args.precision != "auto" else "fp32"
+        print(json.dumps(reports.surrogate(wl, grid=args.grid, precision=prec)), flush=True)
         return
     from synth import make_system, workload
     from paper_2306_16493_amd import Context
