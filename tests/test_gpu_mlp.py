@@ -26,7 +26,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("nout,members", [(1, 2), (3, 3)])
+@pytest.mark.parametrize("nout,members", [(1, 2), (3, 3), (4, 1), (2, 5)])
 def test_gradient_vs_fp64_reference(ctx, nout, members):
     import torch
     from paper_2306_16493_amd.eph import Mlp
