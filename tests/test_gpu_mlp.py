@@ -73,6 +73,41 @@ def test_forward_and_training(ctx):
         assert np.max(np.abs(pred[e] - yr)) < 1e-4 * np.max(np.abs(yr)) + 1e-5
 
 
+def test_invalid_sizes_leave_the_ensemble_usable(ctx):
+    """Sizes outside the documented ranges are rejected with EPH_E_INVALID
+    (members 1..64, outputs 1..MAX_TEMPS, batch a positive multiple of
+    32, steps >= 0, lr > 0, gradient samples a positive multiple of 32); the
+    ensemble is untouched and trains afterwards."""
+    import torch
+    from paper_2306_16493_amd import eph
+    from paper_2306_16493_amd.eph import Mlp, EphError
+    for members, nout in ((0, 1), (65, 1), (2, 0), (2, eph.MAX_TEMPS + 1)):
+        with pytest.raises(EphError) as ei:
+            Mlp(ctx, members=members, n_out=nout, seed=1)
+        assert ei.value.code == eph.EPH_E_INVALID
+    m = Mlp(ctx, members=2, n_out=eph.MAX_TEMPS, seed=9)
+    p0 = m.get_params()
+    rng = np.random.default_rng(3)
+    n = 640
+    xh = rng.uniform(-1, 1, (n, ref.NIN)).astype(np.float32)
+    yh = np.stack([np.sin(2 * xh[:, t]) + 0.3 * xh[:, t + 4] for t in range(eph.MAX_TEMPS)], axis=1)
+    x = torch.tensor(xh, device="cuda")
+    y = torch.tensor(yh.astype(np.float32), device="cuda")
+    for kw in (dict(steps=1, batch=48), dict(steps=1, batch=0), dict(steps=-1, batch=64),
+               dict(steps=1, batch=64, lr=0.0)):
+        with pytest.raises(EphError) as ei:
+            m.train(x, y, **kw)
+        assert ei.value.code == eph.EPH_E_INVALID
+    with pytest.raises(EphError) as ei:
+        m.gradient(x[:40], y[:40])
+    assert ei.value.code == eph.EPH_E_INVALID
+    assert np.array_equal(m.get_params(), p0)
+    l0 = m.train(x, y, steps=1, batch=64, lr=1e-3)
+    l1 = m.train(x, y, steps=300, batch=64, lr=2e-3)
+    assert np.all(np.isfinite(l1)) and np.all(l1 < l0)
+    m.close()
+
+
 def test_surrogate_with_fallback_vs_plain():
     """Al-like 24^3: the ensemble fit on plain rates of a seeded k subset,
     with plain fallback where the members disagree by more than 1%, gives
