@@ -1,7 +1,7 @@
 // Ensemble MLP surrogate of the scattering rates (gfx950, FP32).
 //
 // Members are independent multilayer perceptrons
-//   x (7) -> 128 -> 128 -> 128 -> n_out,   SiLU between layers,
+//   x (10) -> 128 -> 128 -> 128 -> n_out,   SiLU between layers,
 // trained by Adam on the mean squared error of normalised log(1/tau).
 // Parameter layout of one member (row-major W[out][in]):
 //   W1 b1 | W2 b2 | W3 b3 | W4 b4.
@@ -10,16 +10,19 @@
 //                      forward through the layers with pre-activations kept
 //                      in LDS, backward, and the tile's gradient written to
 //                      its own slot (no atomics).  The hidden 128 x 128
-//                      weights are staged in LDS (padded rows, loads of the
-//                      next layer's issued before the current one's sums) and
-//                      every thread owns a 4 x 4 (forward, input gradient) or
-//                      8 x 8 (weight gradient) block fed by float4 LDS reads;
+//                      weights are staged in LDS (padded rows, the next
+//                      layer's loads issued before the current one's
+//                      products); every layer product (forward, input and
+//                      weight gradients, output layer) runs on 16 x 16 x 4
+//                      FP32 MFMA tiles, the first layer's forward on the
+//                      vector units;
 //   mlp_adam_kernel    per parameter: the tile gradients summed in tile
 //                      order, then the Adam update;
 //   mlp_forward_kernel inference for all members;
 //   helpers for features, normalisation, ensemble blending and merging.
-// Minibatches are drawn with a counter-based hash (splitmix64), so training
-// is reproducible for a given seed.
+// Minibatch indices are the high half of a counter-based hash (splitmix64 of
+// seed, member, step and position) times n, so training is reproducible for
+// a given seed.
 #include <math.h>
 
 #include "internal.h"
@@ -29,7 +32,7 @@ namespace mlp {
 
 constexpr int NIN = 10;  // features: (sin, cos)(2 pi k_i/N) x 3, eps - mu, v x 3
 constexpr int H = 128;
-constexpr int TS = 32;       // samples per workgroup tile
+constexpr int TS = 32;       // samples per workgroup tile (inference)
 constexpr int THREADS = 256;
 constexpr int MAXOUT = EPH_MAX_TEMPS;
 
