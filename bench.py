@@ -149,7 +149,7 @@ def main():
                     help="instead of the bench line, measure the FP32/BF16x3 forms or the surrogate on "
                          "their own workloads (one JSON line)")
     ap.add_argument("--subset-frac", type=float, default=0.01, help="k-point fraction of --report precision")
-    ap.add_argument("--train-fracs", default="0.02,0.05", help="training fractions of --report surrogate-sweep")
+    ap.add_argument("--train-fracs", default="0.01,0.02,0.05", help="training fractions of --report surrogate-sweep")
     ap.add_argument("--thresholds", default="0.01,0.02,0.05", help="spread thresholds of --report surrogate-sweep")
     ap.add_argument("--reference", default=None,
                     help="JSON with the sigma and time of the full plain run (--report surrogate-sweep; measured "
