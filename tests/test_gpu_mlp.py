@@ -71,6 +71,43 @@ def test_forward_and_training(ctx):
         yr, _, _ = ref.forward(pr[e].astype(np.float64), (x[:256] - xm) / xs, 2)
         yr = yr * ys + ym
         assert np.max(np.abs(pred[e] - yr)) < 1e-4 * np.max(np.abs(yr)) + 1e-5
+        # a ragged count (two full tiles and a partial one) gives the same rows
+        pr77 = m.predict(xt[:77]).cpu().numpy()
+        assert pr77.shape == (2, 77, 2)
+        assert np.max(np.abs(pr77[e] - yr[:77])) < 1e-4 * np.max(np.abs(yr)) + 1e-5
+    assert m.predict(xt[:0]).shape == (2, 0, 2)
+
+
+def test_blend_against_numpy(ctx):
+    """eph_mlp_blend: per state and output the ensemble mean of exp(y) and
+    the relative spread (population standard deviation over the mean), the
+    state flagged where the largest spread over outputs exceeds the
+    threshold; a ragged count of states and an empty one."""
+    import torch
+    from paper_2306_16493_amd.eph import Mlp
+    members, nout = 5, 3
+    m = Mlp(ctx, members=members, n_out=nout, seed=2)
+    rng = np.random.default_rng(17)
+    for n in (77, 0):
+        # members agree up to a per-state noise of 0..5 % in log space
+        y = rng.normal(-3.0, 1.0, (1, n, nout)) + rng.normal(0.0, 1.0, (members, n, nout)) * \
+            rng.uniform(0.0, 0.05, (1, n, 1))
+        y = y.astype(np.float32)
+        r = np.exp(y.astype(np.float64))
+        mean = r.mean(axis=0)
+        spread = (np.sqrt(np.maximum((r * r).mean(axis=0) - mean * mean, 0.0)) / mean).max(axis=1)
+        srt = np.sort(spread)
+        thr = float(0.5 * (srt[n // 2] + srt[n // 2 + 1])) if n else 0.05  # between two states
+        if n:
+            assert np.min(np.abs(spread - thr)) > 1e-9  # no state on the edge
+        it, flag, nf = m.blend(torch.tensor(y, device="cuda"), thr)
+        it, flag = it.cpu().numpy(), flag.cpu().numpy()
+        assert it.shape == (nout, n) and flag.shape == (n,)
+        if n:
+            assert np.allclose(it, mean.T, rtol=1e-12, atol=0.0)
+            assert np.array_equal(flag.astype(bool), spread > thr)
+        assert nf == int(np.sum(spread > thr))
+    m.close()
 
 
 def test_invalid_sizes_leave_the_ensemble_usable(ctx):
