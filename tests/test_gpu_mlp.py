@@ -162,8 +162,10 @@ def test_surrogate_with_fallback_vs_plain():
     full = gpu_run(c, c.params(24, mu, temps, w.eta, lo, hi))
     res = full["res"]
     sig_full = c.conductivity(res.energy, res.vel, res.inv_tau.reshape(-1), mu, temps, 24 ** 3)
+    # fallback in chunks of 1000 k points: several rates calls merged in turn
     r = surrogate.run(c, 24, mu, temps, w.eta, lo, hi, train_frac=0.25, steps=6000, batch=512, decay=True,
-                      threshold=0.01, log=log)
+                      threshold=0.01, log=log, fallback_chunk=1000)
+    assert r.n_fallback_k > 2000
     err = rel_err(r.sigma, sig_full)
     log(f"[surrogate] sigma rel err {err:.3e}; flagged {r.n_flagged}/{r.n_states}; times {r.times}")
     assert np.array_equal(r.states[0].cpu().numpy(), full["state_k"])
