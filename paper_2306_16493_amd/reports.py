@@ -164,7 +164,7 @@ def surrogate(workload_name="al_fcc_200", train_frac=0.02, chunks=8, threshold=0
     return out
 
 
-def surrogate_sweep(workload_name="al_fcc_200", train_fracs=(0.02, 0.05), thresholds=(0.01, 0.02, 0.05),
+def surrogate_sweep(workload_name="al_fcc_200", train_fracs=(0.01, 0.02, 0.05), thresholds=(0.01, 0.02, 0.05),
                     members=5, steps=30000, batch=512, decay=True, seed=1649307, grid=None, precision="fp32",
                     ref=None, chunks=8):
     """The surrogate over training fractions and spread thresholds against
