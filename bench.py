@@ -162,7 +162,7 @@ def main():
                     help="only run a 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the rate path runs on one GPU; --gpus must be 1"}), flush=True)
         sys.exit(2)
 
     if args.source_sha:
