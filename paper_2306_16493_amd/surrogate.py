@@ -1,4 +1,4 @@
-"""Surrogate-with-fallback driver of the scattering rates (argument
+"""Surrogate-with-fallback orchestration of the scattering rates (argument
 marshalling and scheduling only; the arithmetic is in the HIP kernels).
 
 Steps, each a C-ABI call:
